@@ -1,0 +1,383 @@
+"""Seeded synthetic traffic-engineering inputs.
+
+This module builds the inputs of the TE problem of the paper (section "TE
+Formulation"): a capacitated directed link set, a demand per ordered node pair
+and, per demand, a set of precomputed paths.  It stands in for the paper's
+topologies and traces (its "Experiment Setup" section: public topologies with
+gravity-model demands, production WANs, k-shortest paths with k=4), none of
+which is available here.  It holds none of the solver's arithmetic and is the
+only code shared by the oracle-side tests and the GPU-side tests.
+
+Recipes (all seeded through ``numpy.random.SeedSequence``):
+
+* Waxman topology: nodes uniform in the unit square, an undirected edge (u, v)
+  with probability beta_w * exp(-d(u, v) / (alpha_w * L)), L the largest
+  pairwise distance.  beta_w is calibrated per draw so that the expected edge
+  count equals the requested link count; draws are repeated until the graph is
+  connected and the edge count is within 10% of the target.  Each undirected
+  link becomes two arcs with the same capacity.
+* Gravity demands: D_st proportional to w_s * w_t for all ordered pairs with at
+  least one path, node weights w lognormal (or 1 + Pareto for the hierarchical
+  graph).
+* Paths: the first k simple paths in (cost, node sequence) order, cost = hop
+  count or Euclidean length (Yen's algorithm, ``ksp.c``).
+* Scale: D = factor * lambda_star * D_gravity, where lambda_star is the largest
+  lambda for which lambda * D_gravity is routable on the given paths (max
+  concurrent flow, one LP).  The tightest path-restricted cut is then
+  ``factor`` times oversubscribed.
+"""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import json
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LAMBDA_CACHE = os.path.join(_HERE, "lambda_star.json")
+
+
+@dataclass
+class Instance:
+    """One TE instance in the layout the C ABI takes.
+
+    link i is the arc link_src[i] -> link_dst[i] with capacity[i];
+    paths of demand c are path ids demand_path_ptr[c] .. demand_path_ptr[c+1]-1;
+    path r uses links path_links[path_ptr[r] : path_ptr[r+1]] in path order.
+    """
+    name: str
+    n_nodes: int
+    link_src: np.ndarray
+    link_dst: np.ndarray
+    capacity: np.ndarray
+    demand_src: np.ndarray
+    demand_dst: np.ndarray
+    demand: np.ndarray
+    path_ptr: np.ndarray
+    path_links: np.ndarray
+    demand_path_ptr: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_links(self) -> int:
+        return int(self.capacity.shape[0])
+
+    @property
+    def n_demands(self) -> int:
+        return int(self.demand.shape[0])
+
+    @property
+    def n_paths(self) -> int:
+        return int(self.path_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.path_links.shape[0])
+
+    def fingerprint(self) -> str:
+        h = hashlib.sha256()
+        for a in (self.link_src, self.link_dst, self.capacity, self.demand, self.path_ptr,
+                  self.path_links, self.demand_path_ptr):
+            h.update(np.ascontiguousarray(a).tobytes())
+        return h.hexdigest()[:16]
+
+    def summary(self) -> str:
+        return (f"{self.name}: nodes={self.n_nodes} links={self.n_links} demands={self.n_demands} "
+                f"paths={self.n_paths} nnz={self.nnz}")
+
+
+def make_instance(name, n_nodes, link_src, link_dst, capacity, demand_src, demand_dst, demand,
+                  paths, meta=None) -> Instance:
+    """paths: list (one entry per demand) of lists of link-id lists."""
+    pp = [0]
+    dp = [0]
+    links = []
+    for plist in paths:
+        for p in plist:
+            links.extend(int(e) for e in p)
+            pp.append(len(links))
+        dp.append(len(pp) - 1)
+    return Instance(
+        name=name, n_nodes=int(n_nodes),
+        link_src=np.asarray(link_src, dtype=np.int32), link_dst=np.asarray(link_dst, dtype=np.int32),
+        capacity=np.asarray(capacity, dtype=np.float64),
+        demand_src=np.asarray(demand_src, dtype=np.int32), demand_dst=np.asarray(demand_dst, dtype=np.int32),
+        demand=np.asarray(demand, dtype=np.float64),
+        path_ptr=np.asarray(pp, dtype=np.int64), path_links=np.asarray(links, dtype=np.int32),
+        demand_path_ptr=np.asarray(dp, dtype=np.int32), meta=dict(meta or {}))
+
+
+# ----------------------------------------------------------------------------------------------
+# k shortest paths (C helper)
+# ----------------------------------------------------------------------------------------------
+_ksp_lib = None
+
+
+def _ksp():
+    global _ksp_lib
+    if _ksp_lib is None:
+        path = os.path.join(_HERE, "libksp.so")
+        if not os.path.exists(path):
+            build_ksp()
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        lib.ksp_batch.restype = ctypes.c_int
+        lib.ksp_batch.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P, P, ctypes.c_int, P, P, P,
+                                  ctypes.c_int, P, P, P]
+        _ksp_lib = lib
+    return _ksp_lib
+
+
+def build_ksp() -> str:
+    import subprocess
+    out = os.path.join(_HERE, "libksp.so")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", os.path.join(_HERE, "ksp.c"),
+                           "-o", out])
+    return out
+
+
+def k_shortest_paths(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, k_per, chunk=8192):
+    """Returns, per pair, a list of paths, each a list of arc ids (first k in (cost, sequence) order)."""
+    arc_src = np.ascontiguousarray(arc_src, dtype=np.int32)
+    arc_dst = np.ascontiguousarray(arc_dst, dtype=np.int32)
+    weight = np.ascontiguousarray(weight, dtype=np.float64)
+    m = arc_src.shape[0]
+    n = int(n_nodes)
+    order = np.lexsort((arc_dst, arc_src))
+    out_ptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(out_ptr, arc_src + 1, 1)
+    out_ptr = np.cumsum(out_ptr).astype(np.int32)
+    out_arc = np.ascontiguousarray(order, dtype=np.int32)
+    order_in = np.lexsort((arc_src, arc_dst))
+    in_ptr = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(in_ptr, arc_dst + 1, 1)
+    in_ptr = np.cumsum(in_ptr).astype(np.int32)
+    in_arc = np.ascontiguousarray(order_in, dtype=np.int32)
+    pair_src = np.ascontiguousarray(pair_src, dtype=np.int32)
+    pair_dst = np.ascontiguousarray(pair_dst, dtype=np.int32)
+    k_per = np.ascontiguousarray(np.broadcast_to(np.asarray(k_per, dtype=np.int32), pair_src.shape))
+    kmax = int(k_per.max()) if k_per.size else 1
+    lib = _ksp()
+    res = []
+    hop_cap = max(n - 1, 1)
+    for s0 in range(0, pair_src.shape[0], chunk):
+        s1 = min(s0 + chunk, pair_src.shape[0])
+        q = s1 - s0
+        npaths = np.zeros(q, dtype=np.int32)
+        hops = np.zeros(q * kmax, dtype=np.int32)
+        arcs = np.zeros(q * kmax * hop_cap, dtype=np.int32)
+        ps = np.ascontiguousarray(pair_src[s0:s1])
+        pt = np.ascontiguousarray(pair_dst[s0:s1])
+        kp = np.ascontiguousarray(k_per[s0:s1])
+        err = lib.ksp_batch(n, m, arc_src.ctypes.data, arc_dst.ctypes.data, weight.ctypes.data,
+                            out_ptr.ctypes.data, out_arc.ctypes.data, in_ptr.ctypes.data, in_arc.ctypes.data,
+                            q, ps.ctypes.data, pt.ctypes.data, kp.ctypes.data, kmax,
+                            npaths.ctypes.data, hops.ctypes.data, arcs.ctypes.data)
+        if err:
+            raise RuntimeError("ksp_batch failed")
+        for i in range(q):
+            plist = []
+            for j in range(npaths[i]):
+                h = hops[i * kmax + j]
+                base = (i * kmax + j) * hop_cap
+                plist.append(arcs[base:base + h].tolist())
+            res.append(plist)
+    return res
+
+
+# ----------------------------------------------------------------------------------------------
+# topology and demand recipes
+# ----------------------------------------------------------------------------------------------
+def _connected(n, edges) -> bool:
+    adj = [[] for _ in range(n)]
+    for u, v in edges:
+        adj[u].append(v)
+        adj[v].append(u)
+    seen = {0}
+    stack = [0]
+    while stack:
+        u = stack.pop()
+        for v in adj[u]:
+            if v not in seen:
+                seen.add(v)
+                stack.append(v)
+    return len(seen) == n
+
+
+def waxman(n, target_links, rng, alpha_w=0.4, tol=0.1, max_tries=1000, box=(0.0, 0.0, 1.0, 1.0)):
+    """Undirected Waxman graph; returns (positions [n,2], edge list [(u, v) with u < v])."""
+    for _ in range(max_tries):
+        x0, y0, x1, y1 = box
+        pos = np.column_stack([rng.uniform(x0, x1, n), rng.uniform(y0, y1, n)])
+        iu, iv = np.triu_indices(n, 1)
+        d = np.hypot(*(pos[iu] - pos[iv]).T)
+        L = d.max()
+        base = np.exp(-d / (alpha_w * L))
+        beta_w = min(1.0, target_links / base.sum())
+        keep = rng.uniform(size=base.shape) < beta_w * base
+        edges = list(zip(iu[keep].tolist(), iv[keep].tolist()))
+        if abs(len(edges) - target_links) <= tol * target_links and _connected(n, edges):
+            return pos, edges
+    raise RuntimeError("could not draw a connected Waxman graph")
+
+
+def arcs_from_edges(edges, edge_cap, pos=None):
+    """Each undirected edge (u, v) -> arcs u->v and v->u, same capacity; arc weights = Euclidean length."""
+    src, dst, cap, w = [], [], [], []
+    for (u, v), c in zip(edges, edge_cap):
+        for a, b in ((u, v), (v, u)):
+            src.append(a)
+            dst.append(b)
+            cap.append(float(c))
+            w.append(float(np.hypot(*(pos[a] - pos[b]))) if pos is not None else 1.0)
+    return (np.asarray(src, np.int32), np.asarray(dst, np.int32), np.asarray(cap, np.float64),
+            np.asarray(w, np.float64))
+
+
+def gravity(weights, pair_src, pair_dst):
+    g = weights[pair_src] * weights[pair_dst]
+    return g / g.sum()
+
+
+def max_concurrent_flow(inst: Instance, base_demand: np.ndarray) -> float:
+    """lambda_star = max lambda such that lambda * base_demand is routable on the instance's paths."""
+    from scipy.optimize import linprog
+    from scipy.sparse import coo_matrix
+    P, D, E = inst.n_paths, inst.n_demands, inst.n_links
+    path_of_inc = np.repeat(np.arange(P), np.diff(inst.path_ptr))
+    dem_of_path = np.repeat(np.arange(D), np.diff(inst.demand_path_ptr))
+    # rows 0..E-1: capacity; rows E..E+D-1: lambda*D_c - S_c <= 0
+    rows = np.concatenate([inst.path_links, E + dem_of_path, E + np.arange(D)])
+    cols = np.concatenate([path_of_inc, np.arange(P), np.full(D, P)])
+    vals = np.concatenate([np.ones(inst.nnz), -np.ones(P), base_demand])
+    A = coo_matrix((vals, (rows, cols)), shape=(E + D, P + 1)).tocsr()
+    b = np.concatenate([inst.capacity, np.zeros(D)])
+    c = np.zeros(P + 1)
+    c[P] = -1.0
+    res = linprog(c, A_ub=A, b_ub=b, bounds=[(0, None)] * (P + 1), method="highs")
+    if res.status != 0:
+        raise RuntimeError(f"lambda_star LP failed: {res.message}")
+    return float(res.x[P])
+
+
+def _lambda_cached(key: str, compute) -> float:
+    cache = {}
+    if os.path.exists(_LAMBDA_CACHE):
+        with open(_LAMBDA_CACHE) as f:
+            cache = json.load(f)
+    if key in cache:
+        return float(cache[key])
+    val = compute()
+    cache[key] = repr(val)
+    try:
+        with open(_LAMBDA_CACHE, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+    except OSError:
+        pass
+    return val
+
+
+def _assemble(name, n, src, dst, cap, pairs, base, paths, factor, meta):
+    keep = [i for i, p in enumerate(paths) if len(p) > 0]
+    ps = np.asarray([pairs[i][0] for i in keep], np.int32)
+    pt = np.asarray([pairs[i][1] for i in keep], np.int32)
+    base = np.asarray([base[i] for i in keep], np.float64)
+    base = base / base.sum()
+    kept_paths = [paths[i] for i in keep]
+    inst = make_instance(name, n, src, dst, cap, ps, pt, base, kept_paths, meta)
+    key = f"{name}:{inst.fingerprint()}"
+    lam = _lambda_cached(key, lambda: max_concurrent_flow(inst, base))
+    inst.demand = factor * lam * base
+    inst.meta.update(lambda_star=lam, scale_factor=factor, dropped_pairs=len(pairs) - len(keep))
+    return inst
+
+
+def config1(seed: int = 0) -> Instance:
+    """20-node Waxman, ~60 links, capacities {10,40,100}, all 380 pairs, lognormal(0,1) gravity,
+    1.5x the path-restricted max concurrent flow, k=4 hop-shortest paths."""
+    rng = np.random.default_rng(np.random.SeedSequence([1, seed]))
+    n = 20
+    pos, edges = waxman(n, 60, rng)
+    ecap = rng.choice([10.0, 40.0, 100.0], size=len(edges))
+    src, dst, cap, _ = arcs_from_edges(edges, ecap)
+    w = rng.lognormal(0.0, 1.0, n)
+    pairs = [(s, t) for s in range(n) for t in range(n) if s != t]
+    base = gravity(w, np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs]))
+    paths = k_shortest_paths(n, src, dst, np.ones(len(src)), [p[0] for p in pairs], [p[1] for p in pairs], 4)
+    return _assemble(f"config1/s{seed}", n, src, dst, cap, pairs, base, paths, 1.5,
+                     dict(kind="config1", seed=seed, edges=len(edges)))
+
+
+def config2(seed: int = 0) -> Instance:
+    """150-node Waxman, ~600 links, capacities {100,400}, all 22,350 pairs, lognormal(0,1.5) gravity,
+    1.3x the path-restricted max concurrent flow, k=8 Euclidean-latency-shortest paths."""
+    rng = np.random.default_rng(np.random.SeedSequence([2, seed]))
+    n = 150
+    pos, edges = waxman(n, 600, rng)
+    ecap = rng.choice([100.0, 400.0], size=len(edges))
+    src, dst, cap, wgt = arcs_from_edges(edges, ecap, pos)
+    w = rng.lognormal(0.0, 1.5, n)
+    pairs = [(s, t) for s in range(n) for t in range(n) if s != t]
+    base = gravity(w, np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs]))
+    paths = k_shortest_paths(n, src, dst, wgt, [p[0] for p in pairs], [p[1] for p in pairs], 8)
+    return _assemble(f"config2/s{seed}", n, src, dst, cap, pairs, base, paths, 1.3,
+                     dict(kind="config2", seed=seed, edges=len(edges)))
+
+
+def config4_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
+    """Failure scenarios on the config-1 topology: 1-3 undirected links cut, each demand times
+    exp(N(0, 0.3)), paths recomputed with k_c ~ U{2..8} hop-shortest paths, disconnected pairs dropped."""
+    base = config1(base_seed)
+    n = base.n_nodes
+    n_edges = base.n_links // 2
+    ss = np.random.SeedSequence([4, seed]).spawn(n_scen)
+    out = []
+    for i, s in enumerate(ss):
+        rng = np.random.default_rng(s)
+        ncut = int(rng.integers(1, 4))
+        cut = set(rng.choice(n_edges, size=ncut, replace=False).tolist())
+        keep_arcs = [a for a in range(base.n_links) if (a // 2) not in cut]
+        remap = {a: j for j, a in enumerate(keep_arcs)}
+        src = base.link_src[keep_arcs]
+        dst = base.link_dst[keep_arcs]
+        cap = base.capacity[keep_arcs]
+        dem = base.demand * np.exp(rng.normal(0.0, 0.3, base.n_demands))
+        kper = rng.integers(2, 9, base.n_demands)
+        paths = k_shortest_paths(n, src, dst, np.ones(len(src)), base.demand_src, base.demand_dst, kper)
+        keep = [c for c in range(base.n_demands) if len(paths[c]) > 0]
+        inst = make_instance(f"config4/s{seed}/{i}", n, src, dst, cap, base.demand_src[keep],
+                             base.demand_dst[keep], dem[keep], [paths[c] for c in keep],
+                             dict(kind="config4", seed=seed, scenario=i, cut=sorted(cut),
+                                  dropped_pairs=base.n_demands - len(keep)))
+        del remap
+        out.append(inst)
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# small closed-form instances (for pins)
+# ----------------------------------------------------------------------------------------------
+def parking_lot(L: int, demand: float = 10.0, cap: float = 1.0) -> Instance:
+    """Chain of L unit links; demand 0 uses all L links, demand i (1..L) uses link i-1 only."""
+    src = np.arange(L, dtype=np.int32)
+    dst = src + 1
+    paths = [[list(range(L))]] + [[[i]] for i in range(L)]
+    dsrc = [0] + list(range(L))
+    ddst = [L] + list(range(1, L + 1))
+    return make_instance(f"parking_lot{L}", L + 1, src, dst, np.full(L, cap), dsrc, ddst,
+                         np.full(L + 1, demand), paths)
+
+
+def shared_link(demands, cap: float = 1.0) -> Instance:
+    """One link shared by single-path demands."""
+    n = len(demands)
+    return make_instance("shared_link", 2, [0], [1], [cap], [0] * n, [1] * n, demands, [[[0]] for _ in range(n)])
+
+
+def parallel_paths(caps, demand) -> Instance:
+    """One demand over disjoint single-link paths."""
+    m = len(caps)
+    return make_instance("parallel", 2, [0] * m, [1] * m, caps, [0], [1], [demand], [[[i] for i in range(m)]])
