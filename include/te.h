@@ -1,0 +1,197 @@
+/*
+ * te.h -- C ABI of the GATE traffic-engineering solver for AMD Instinct MI355X (gfx950).
+ *
+ * The library solves the path-based multicommodity-flow TE problem of the
+ * paper "GATE: GPU-Accelerated Traffic Engineering for the WAN" (section 3.1,
+ * "TE Formulation"):
+ *
+ *     maximise   sum_c U_alpha(S_c),      S_c = sum_{r in P_c} x_r,
+ *     subject to S_c <= D_c               (demand constraint)
+ *                sum_{r : e in r} x_r <= C_e   (capacity constraint)
+ *                x_r >= 0                 (non-negativity)
+ *
+ * with the alpha-fair utility U_alpha(b) = (b^(1-alpha) - 1)/(1 - alpha)
+ * (alpha = 0: max-flow, 1: proportional fairness, infinity: max-min
+ * fairness), by the paper's iterative decomposition (section 3.3, Algorithm 1):
+ * per iteration a gather of per-link prices along every path, a per-demand
+ * update of its split (sum equation of appendix B.2 solved by Newton-bisection,
+ * rate update of section 3.3), a segmented sum of path rates into link loads
+ * and a per-link capacity/dual update, with the residual-balancing penalty of
+ * section 3.4, alpha-increments (section 3.4) and the feasibility projection
+ * of Algorithm 2 (section 3.5) at the end.
+ *
+ * Conventions
+ *  - Every function returns te_status; nothing is thrown and nothing aborts.
+ *    On a non-OK status te_last_error() gives a message (thread-local).
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - "_dev" pointers are device pointers on the handle's device (for example
+ *    torch tensors); the library never frees them.  Work on them is ordered on
+ *    the hip_stream argument (a hipStream_t, NULL = legacy default stream).
+ *  - A handle may be used by one host thread at a time; separate handles are
+ *    independent.  A handle owns its device buffers until te_destroy.
+ *  - Units: the library divides capacities and demands by s = the largest
+ *    capacity of a link used by some path, iterates in those units, and
+ *    returns rates and sums in the caller's units.
+ *  - Admissible instance (appendix C, Part I(b): every commodity has a path and
+ *    a positive demand, every used link a positive capacity): path_ptr
+ *    non-decreasing from 0, no empty path, link ids in range, no link twice in
+ *    one path, every demand with 1..64 paths, demand > 0 and finite, capacity
+ *    finite everywhere and > 0 on every used link.  Anything else returns
+ *    TE_ERR_INVALID.
+ */
+#ifndef TE_GATE_H
+#define TE_GATE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct te_ctx te_ctx;
+typedef struct te_batch te_batch;
+
+typedef enum {
+  TE_OK = 0,
+  TE_ERR_INVALID = 1, /* argument or instance not admissible */
+  TE_ERR_OOM = 2,     /* device or host allocation failed */
+  TE_ERR_DEVICE = 3,  /* HIP runtime error (no device, launch failure, ...) */
+  TE_ERR_NUMERIC = 4, /* non-finite value reached the state */
+  TE_ERR_STATE = 5    /* call not valid in the handle's state (e.g. te_grad without a recorded solve) */
+} te_status;
+
+/* te_stats.flags */
+enum {
+  TE_CONVERGED = 1,      /* residuals below gamma at the target alpha, or stagnation across an alpha step */
+  TE_HIT_MAX_ITERS = 2,  /* adaptive mode stopped at max_iters */
+  TE_HIT_ALPHA_MAX = 4,  /* an alpha step would have exceeded alpha_max */
+  TE_HIT_BETA_BOUND = 8  /* the residual-balancing rule hit beta_min or beta_max */
+};
+
+/* te_options.engine */
+enum {
+  TE_ENGINE_AUTO = 0,  /* workgroup engine when the instance fits one workgroup's LDS, else graph engine */
+  TE_ENGINE_GRAPH = 1, /* device-wide kernels per iteration, replayed as a captured HIP graph */
+  TE_ENGINE_BLOCK = 2  /* whole solve inside one workgroup, state resident in LDS */
+};
+
+typedef struct {
+  double alpha_target; /* fairness target: INFINITY = max-min (default), 0 = max-flow, 1 = proportional */
+  double gamma;        /* residual threshold of the stop test (section 3.4); default 1e-3 */
+  double beta0;        /* initial penalty (Algorithm 1 optional input); default 1 */
+  double A, C;         /* residual-balancing constants (section 3.6: A = 10, C = 2) */
+  double beta_min;     /* bounds on beta (absolute); default 1e-3 * beta0 and 1e3 * beta0 */
+  double beta_max;
+  int32_t max_iters;   /* adaptive mode: stop after this many iterations (flag TE_HIT_MAX_ITERS) */
+  int32_t alpha_max;   /* largest alpha an increment may reach (flag TE_HIT_ALPHA_MAX); default 64 */
+  int32_t fixed_iters; /* > 0: run exactly this many iterations, no stop test; alpha and beta still adapt */
+  int32_t adapt_beta;  /* 0: keep beta = beta0 */
+  int32_t beta_every;  /* apply the residual-balancing rule after every beta_every-th iteration; default 5 */
+  int32_t project;     /* 1: run the feasibility projection of Algorithm 2 before returning (default) */
+  int32_t engine;      /* TE_ENGINE_* */
+  int32_t record;      /* 1: keep the (beta, alpha) schedule and checkpoints for te_grad */
+  int32_t ckpt_every;  /* te_grad checkpoint spacing in iterations; default 16 */
+  /* Optional replay of a (beta_k, alpha_k) schedule, host arrays of sched_len entries: iteration k
+   * uses beta = sched_beta[k], alpha = sched_alpha[k] (the last entry repeats), no adaptation. */
+  const double *sched_beta;
+  const double *sched_alpha;
+  int32_t sched_len;
+} te_options;
+
+typedef struct {
+  int32_t iters;       /* iterations run */
+  int32_t flags;       /* TE_CONVERGED | ... */
+  int32_t stop_iter;   /* first iteration at which the stop test passed, -1 if never */
+  int32_t engine;      /* engine that ran */
+  double final_alpha;
+  double beta;         /* final penalty */
+  double r, s;         /* last primal and dual residuals (section 3.4) */
+  double max_cap_viol_rel; /* max over links of (load - C)/C before projection */
+  double max_dem_viol_rel; /* max over demands of (S - D)/D before projection */
+  double ms;           /* device time of the solve (init to output), milliseconds */
+} te_stats;
+
+/* Fill *opt with the defaults listed above. */
+void te_default_options(te_options *opt);
+
+/*
+ * Validate an instance on the host without touching any GPU; same rules as
+ * te_create.  Returns TE_OK or TE_ERR_INVALID (message in te_last_error()).
+ *   capacity        [n_links]        link capacities
+ *   path_ptr        [n_paths + 1]    CSR row pointer of the path -> link incidence (int64)
+ *   path_links      [path_ptr[n_paths]] link ids of each path, in path order
+ *   demand_path_ptr [n_demands + 1]  the paths of demand c are demand_path_ptr[c] .. [c+1]-1
+ *   demand          [n_demands]      requested demand D_c
+ */
+te_status te_validate(int32_t n_links, const double *capacity, int32_t n_paths, const int64_t *path_ptr,
+                      const int32_t *path_links, int32_t n_demands, const int32_t *demand_path_ptr,
+                      const double *demand);
+
+/*
+ * Build a solver handle on HIP device hip_device: validates (as te_validate),
+ * normalises units, builds the path -> link CSR and link -> path CSC layouts
+ * and copies them to the device (synchronously).  Host arrays as in
+ * te_validate.  *out receives the handle (NULL on error).
+ */
+te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, const int64_t *path_ptr,
+                    const int32_t *path_links, int32_t n_demands, const int32_t *demand_path_ptr,
+                    const double *demand, int32_t hip_device, te_ctx **out);
+
+/* Replace capacities and/or demands (host arrays, nullable) of an existing handle; same validity rules.
+ * A warm start from the previous allocation is then te_solve with x0_dev. */
+te_status te_update(te_ctx *ctx, const double *capacity, const double *demand);
+
+/*
+ * Run Algorithm 1 (and Algorithm 2 if opt->project) on the handle's instance.
+ *   opt        options (NULL = defaults)
+ *   hip_stream hipStream_t to order the work on
+ *   x0_dev     nullable [n_paths] float warm start in caller units (default D_c / |P_c|)
+ *   x_out_dev  [n_paths] float: path rates, caller units
+ *   S_out_dev  nullable [n_demands] float: per-demand sums of x_out
+ *   stats      nullable; when given the call synchronises the stream and fills it
+ */
+te_status te_solve(te_ctx *ctx, const te_options *opt, void *hip_stream, const float *x0_dev, float *x_out_dev,
+                   float *S_out_dev, te_stats *stats);
+
+/*
+ * Vector-Jacobian product through the last solve run with opt->record = 1 and
+ * opt->fixed_iters = K: the unprojected sums S^(K) as a function of capacities
+ * and demands, with the recorded (beta, alpha) schedule and the unit scale
+ * held fixed.
+ *   dS_dev  [n_demands] float cotangent on S^(K), caller units (ones: total throughput;
+ *           1/S: sum of log-allocations)
+ *   dC_dev  [n_links]   double gradient with respect to capacities (caller units)
+ *   dD_dev  [n_demands] double gradient with respect to demands
+ * Recomputes the forward iterations segment by segment from checkpoints taken every
+ * opt->ckpt_every iterations.  TE_ERR_STATE if no recorded solve exists.
+ */
+te_status te_grad(te_ctx *ctx, void *hip_stream, const float *dS_dev, double *dC_dev, double *dD_dev);
+
+/*
+ * Batched solves: n instances (handles on the same device, used read-only) in one
+ * launch of the workgroup engine, one workgroup per instance, each with its own
+ * beta / alpha / stop state.  Instances too large for one workgroup's LDS are
+ * rejected with TE_ERR_INVALID.
+ */
+te_status te_create_batch(int32_t n, te_ctx *const *instances, te_batch **out);
+
+/*   x_out_dev  [sum of n_paths] float, instances concatenated in order
+ *   S_out_dev  nullable [sum of n_demands] float
+ *   stats      nullable [n] te_stats, synchronises the stream when given */
+te_status te_solve_batch(te_batch *batch, const te_options *opt, void *hip_stream, float *x_out_dev,
+                         float *S_out_dev, te_stats *stats);
+
+void te_destroy(te_ctx *ctx);
+void te_destroy_batch(te_batch *batch);
+
+/* Sizes of a handle: n_links, n_paths, n_demands, nnz, max paths per demand, engine AUTO would pick. */
+te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [6] */);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *te_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TE_GATE_H */

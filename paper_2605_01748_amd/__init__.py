@@ -1,0 +1,269 @@
+"""Python binding of the GATE TE solver library (libte_gate.so, C ABI in include/te.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP kernels.  PyTorch
+provides device memory and the current HIP stream.  There is no CPU fallback: if the library is
+missing, importing the solver raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libte_gate.so")
+
+TE_OK, TE_ERR_INVALID, TE_ERR_OOM, TE_ERR_DEVICE, TE_ERR_NUMERIC, TE_ERR_STATE = range(6)
+TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
+ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
+
+API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
+       "te_solve_batch", "te_destroy", "te_destroy_batch", "te_info", "te_last_error"]
+
+
+class TEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"te status {status}: {msg}")
+        self.status = status
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("alpha_target", ctypes.c_double), ("gamma", ctypes.c_double), ("beta0", ctypes.c_double),
+                ("A", ctypes.c_double), ("C", ctypes.c_double), ("beta_min", ctypes.c_double),
+                ("beta_max", ctypes.c_double), ("max_iters", ctypes.c_int32), ("alpha_max", ctypes.c_int32),
+                ("fixed_iters", ctypes.c_int32), ("adapt_beta", ctypes.c_int32), ("beta_every", ctypes.c_int32),
+                ("project", ctypes.c_int32), ("engine", ctypes.c_int32), ("record", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32), ("sched_beta", ctypes.c_void_p), ("sched_alpha", ctypes.c_void_p),
+                ("sched_len", ctypes.c_int32)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("stop_iter", ctypes.c_int32),
+                ("engine", ctypes.c_int32), ("final_alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("r", ctypes.c_double), ("s", ctypes.c_double), ("max_cap_viol_rel", ctypes.c_double),
+                ("max_dem_viol_rel", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def library(path: str = LIB_PATH):
+    """Load libte_gate.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2605_01748_amd.build` "
+                          f"(hipcc, gfx950); there is no fallback path")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int32
+    lib.te_default_options.restype = None
+    lib.te_default_options.argtypes = [ctypes.POINTER(_Options)]
+    lib.te_validate.restype = I
+    lib.te_validate.argtypes = [I, P, I, P, P, I, P, P]
+    lib.te_create.restype = I
+    lib.te_create.argtypes = [I, P, I, P, P, I, P, P, I, ctypes.POINTER(P)]
+    lib.te_update.restype = I
+    lib.te_update.argtypes = [P, P, P]
+    lib.te_solve.restype = I
+    lib.te_solve.argtypes = [P, ctypes.POINTER(_Options), P, P, P, P, ctypes.POINTER(_Stats)]
+    lib.te_grad.restype = I
+    lib.te_grad.argtypes = [P, P, P, P, P]
+    lib.te_create_batch.restype = I
+    lib.te_create_batch.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(P)]
+    lib.te_solve_batch.restype = I
+    lib.te_solve_batch.argtypes = [P, ctypes.POINTER(_Options), P, P, P, P]
+    lib.te_destroy.restype = None
+    lib.te_destroy.argtypes = [P]
+    lib.te_destroy_batch.restype = None
+    lib.te_destroy_batch.argtypes = [P]
+    lib.te_info.restype = I
+    lib.te_info.argtypes = [P, P]
+    lib.te_last_error.restype = ctypes.c_char_p
+    lib.te_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != TE_OK:
+        raise TEError(status, library().te_last_error().decode())
+
+
+@dataclass
+class Options:
+    alpha_target: float = math.inf
+    gamma: float = 1e-3
+    beta0: float = 1.0
+    A: float = 10.0
+    C: float = 2.0
+    beta_min: float | None = None      # default 1e-3 * beta0
+    beta_max: float | None = None      # default 1e3 * beta0
+    max_iters: int = 20000
+    alpha_max: int = 64
+    fixed_iters: int = 0
+    adapt_beta: bool = True
+    beta_every: int = 5
+    project: bool = True
+    engine: int = ENGINE_AUTO
+    record: bool = False
+    ckpt_every: int = 16
+    sched_beta: np.ndarray | None = None
+    sched_alpha: np.ndarray | None = None
+
+    def to_c(self):
+        o = _Options()
+        library().te_default_options(ctypes.byref(o))
+        o.alpha_target = self.alpha_target
+        o.gamma = self.gamma
+        o.beta0 = self.beta0
+        o.A = self.A
+        o.C = self.C
+        o.beta_min = self.beta0 * 1e-3 if self.beta_min is None else self.beta_min
+        o.beta_max = self.beta0 * 1e3 if self.beta_max is None else self.beta_max
+        o.max_iters = self.max_iters
+        o.alpha_max = self.alpha_max
+        o.fixed_iters = self.fixed_iters
+        o.adapt_beta = int(self.adapt_beta)
+        o.beta_every = self.beta_every
+        o.project = int(self.project)
+        o.engine = self.engine
+        o.record = int(self.record)
+        o.ckpt_every = self.ckpt_every
+        keep = []
+        if self.sched_beta is not None:
+            sb = np.ascontiguousarray(self.sched_beta, np.float64)
+            sa = np.ascontiguousarray(self.sched_alpha, np.float64)
+            assert sb.shape == sa.shape
+            o.sched_beta = sb.ctypes.data
+            o.sched_alpha = sa.ctypes.data
+            o.sched_len = sb.shape[0]
+            keep = [sb, sa]
+        return o, keep
+
+
+def _arrays(inst):
+    cap = np.ascontiguousarray(inst.capacity, np.float64)
+    pptr = np.ascontiguousarray(inst.path_ptr, np.int64)
+    plinks = np.ascontiguousarray(inst.path_links, np.int32)
+    dptr = np.ascontiguousarray(inst.demand_path_ptr, np.int32)
+    dem = np.ascontiguousarray(inst.demand, np.float64)
+    return cap, pptr, plinks, dptr, dem
+
+
+def validate(inst):
+    """Host-only admissibility check (te_validate); raises TEError on an invalid instance."""
+    cap, pptr, plinks, dptr, dem = _arrays(inst)
+    _check(library().te_validate(cap.shape[0], cap.ctypes.data, pptr.shape[0] - 1, pptr.ctypes.data,
+                                 plinks.ctypes.data, dem.shape[0], dptr.ctypes.data, dem.ctypes.data))
+
+
+def _stream_ptr(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Problem:
+    """A TE instance resident on one GPU (te_create)."""
+
+    def __init__(self, inst, device: int = 0):
+        lib = library()
+        cap, pptr, plinks, dptr, dem = _arrays(inst)
+        h = ctypes.c_void_p()
+        _check(lib.te_create(cap.shape[0], cap.ctypes.data, pptr.shape[0] - 1, pptr.ctypes.data, plinks.ctypes.data,
+                             dem.shape[0], dptr.ctypes.data, dem.ctypes.data, device, ctypes.byref(h)))
+        self._h = h
+        self.device = device
+        self.n_links, self.n_paths, self.n_demands = cap.shape[0], pptr.shape[0] - 1, dem.shape[0]
+
+    def info(self):
+        sz = np.zeros(6, np.int64)
+        _check(library().te_info(self._h, sz.ctypes.data))
+        return dict(n_links=int(sz[0]), n_paths=int(sz[1]), n_demands=int(sz[2]), nnz=int(sz[3]),
+                    max_paths=int(sz[4]), auto_engine=int(sz[5]))
+
+    def update(self, capacity=None, demand=None):
+        c = None if capacity is None else np.ascontiguousarray(capacity, np.float64)
+        d = None if demand is None else np.ascontiguousarray(demand, np.float64)
+        _check(library().te_update(self._h, None if c is None else c.ctypes.data, None if d is None else d.ctypes.data))
+
+    def solve(self, opts: Options | None = None, x0=None, x_out=None, S_out=None, stats: bool = True, stream=None):
+        """Returns (x [n_paths] float32 cuda tensor, S [n_demands], stats dict or None)."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        opts = opts or Options()
+        o, keep = opts.to_c()
+        if x_out is None:
+            x_out = torch.empty(self.n_paths, dtype=torch.float32, device=dev)
+        if S_out is None:
+            S_out = torch.empty(self.n_demands, dtype=torch.float32, device=dev)
+        x0p = None
+        if x0 is not None:
+            assert x0.dtype == torch.float32 and x0.is_cuda and x0.numel() == self.n_paths
+            x0p = x0.data_ptr()
+        st = _Stats() if stats else None
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_solve(self._h, ctypes.byref(o), sp, x0p, x_out.data_ptr(), S_out.data_ptr(),
+                                  ctypes.byref(st) if st is not None else None))
+        del keep
+        return x_out, S_out, (st.as_dict() if st is not None else None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().te_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many instances solved in one launch of the workgroup engine (te_create_batch)."""
+
+    def __init__(self, problems):
+        lib = library()
+        arr = (ctypes.c_void_p * len(problems))(*[p._h for p in problems])
+        h = ctypes.c_void_p()
+        _check(lib.te_create_batch(len(problems), arr, ctypes.byref(h)))
+        self._h = h
+        self.problems = list(problems)
+        self.device = problems[0].device
+        self.n_paths = [p.n_paths for p in problems]
+        self.n_demands = [p.n_demands for p in problems]
+
+    def solve(self, opts: Options | None = None, stats: bool = True, x_out=None, S_out=None, stream=None):
+        import torch
+        dev = torch.device("cuda", self.device)
+        opts = opts or Options()
+        o, keep = opts.to_c()
+        if x_out is None:
+            x_out = torch.empty(sum(self.n_paths), dtype=torch.float32, device=dev)
+        if S_out is None:
+            S_out = torch.empty(sum(self.n_demands), dtype=torch.float32, device=dev)
+        st = (_Stats * len(self.problems))() if stats else None
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_solve_batch(self._h, ctypes.byref(o), sp, x_out.data_ptr(), S_out.data_ptr(),
+                                        ctypes.cast(st, ctypes.c_void_p) if st is not None else None))
+        del keep
+        return x_out, S_out, ([s.as_dict() for s in st] if st is not None else None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            library().te_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,275 @@
+// te_device.h -- device-side arithmetic of one GATE iteration, shared by both engines.
+//
+// Notation (paper, section 3): x_r path rate, S_c demand sum, D_c demand, C_e capacity,
+// n_r links on path r, n_e paths on link e, beta penalty, alpha fairness, scaled duals
+// u_dem (per demand), u_neg (per path).  The capacity and consensus duals of a link
+// coincide after every sweep (dual_con_{e,r} = dual_cap_e = g_e), and every rate
+// suggestion of a link is y_{e,r} = x_r + q_e with one offset q_e per link, so the
+// per-incidence variables of section 3.2 collapse to the per-link pair (g_e, q_e):
+//   rate-update consensus term   a_r = n_r x_r - sum_{e in r} (g_e - q_e)
+//   rate suggestion + cap dual   g_e' = [g_e + (load_e - C_e) / (1 + n_e)]_+,  q_e' = g_e - g_e'
+// (derived from the exact per-link minimisation with slack_cap, appendix B.1).
+#pragma once
+
+#include <math.h>
+#include "te_internal.h"
+
+namespace te {
+
+enum { F_CONVERGED = 1, F_MAX_ITERS = 2, F_ALPHA_MAX = 4, F_BETA_BOUND = 8 };
+
+// ------------------------------------------------------------------------------------------
+// lane-group reductions (G lanes, power of two, aligned inside one 64-wide wavefront).
+// xor butterflies: every lane of the group ends with the bit-identical sum.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float group_sum(float v, int G) {
+  for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ double group_sum_d(double v, int G) {
+  for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int m = 1; m < 64; m <<= 1) v = fmax(v, __shfl_xor(v, m, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------------------------------
+// per-demand update: the sum equation of appendix B.2 and the rate update of section 3.3.
+// The commodity sub-problem's stationarity in x_r reads n_r x_r - [u_neg_r - x_r]_+ = a_r - h(S),
+// h(S) = [S - D + u_dem]_+ - S^-alpha / beta; xi_r inverts the left side; the root of
+// F(S) = sum_r xi_r(a_r - h(S)) - S (continuous, strictly decreasing) gives S, then x.
+// ------------------------------------------------------------------------------------------
+struct Lane {
+  float a;      // a_r
+  float un;     // u_neg_r (current beta scale)
+  float n;      // n_r
+  float rn;     // 1 / n_r
+  float rn1;    // 1 / (n_r + 1)
+  bool on;      // lane holds a path of the demand
+};
+
+struct Dem {
+  float D, u, alpha, binv;  // demand, u_dem (current scale), alpha, 1/beta
+};
+
+__device__ __forceinline__ float pow_neg_alpha(float S, float alpha) {
+  return alpha == 0.f ? 1.f : exp2f(-alpha * log2f(S));
+}
+
+__device__ __forceinline__ float xi_of(float b, const Lane &L) {
+  return (b >= L.n * L.un) ? b * L.rn : (b + L.un) * L.rn1;
+}
+
+__device__ __forceinline__ float h_of(float S, const Dem &c) {
+  return fmaxf(S - c.D + c.u, 0.f) - pow_neg_alpha(S, c.alpha) * c.binv;
+}
+
+// F(S) and F'(S) summed over the group (uniform inside the group).
+__device__ __forceinline__ void F_eval(float S, const Lane &L, const Dem &c, int G, float &F, float &dF) {
+  if (c.alpha > 0.f && !(S > 0.f)) {
+    F = INFINITY;
+    dF = -INFINITY;
+    return;
+  }
+  float t = S - c.D + c.u;
+  float pw = pow_neg_alpha(S, c.alpha);
+  float h = fmaxf(t, 0.f) - pw * c.binv;
+  float dh = (t > 0.f ? 1.f : 0.f) + (c.alpha > 0.f ? c.alpha * pw * c.binv / S : 0.f);
+  float b = L.a - h;
+  bool hi_branch = b >= L.n * L.un;
+  float v = L.on ? (hi_branch ? b * L.rn : (b + L.un) * L.rn1) : 0.f;
+  float dv = L.on ? (hi_branch ? L.rn : L.rn1) : 0.f;
+  v = group_sum(v, G);
+  dv = group_sum(dv, G);
+  F = v - S;
+  dF = -dh * dv - 1.f;
+}
+
+// Safeguarded Newton (appendix B.2): bracket [lo, hi] with F(lo) > 0 > F(hi) grown from the
+// warm start, Newton steps while they stay inside, bisection otherwise.
+__device__ float sum_root(float S0, const Lane &L, const Dem &c, int G, int *steps) {
+  if (c.alpha > 0.f && !(S0 > 0.f)) S0 = fmaxf(c.D, 1e-6f);
+  float F0, d0;
+  F_eval(S0, L, c, G, F0, d0);
+  *steps = 0;
+  if (F0 == 0.f) return S0;
+  float lo, hi;
+  float Fs, dFs, S;
+  if (F0 > 0.f) {
+    lo = S0;
+    float Flo = F0, dlo = d0;
+    float step = fmaxf(fabsf(S0), 1e-6f);
+    hi = S0 + step;
+    for (int i = 0; i < 160; ++i) {
+      float Fh, dh;
+      hi = S0 + step;
+      F_eval(hi, L, c, G, Fh, dh);
+      if (Fh == 0.f) return hi;
+      if (Fh < 0.f) break;
+      lo = hi;
+      Flo = Fh;
+      dlo = dh;
+      step *= 2.f;
+    }
+    S = lo;
+    Fs = Flo;
+    dFs = dlo;
+  } else {
+    hi = S0;
+    float Fhi = F0, dhi = d0;
+    if (c.alpha > 0.f) {
+      lo = S0;
+      for (int i = 0; i < 160; ++i) {
+        float Fl, dl;
+        lo *= 0.5f;
+        F_eval(lo, L, c, G, Fl, dl);
+        if (Fl == 0.f) return lo;
+        if (Fl > 0.f) break;
+        hi = lo;
+        Fhi = Fl;
+        dhi = dl;
+      }
+    } else {
+      float step = fmaxf(fabsf(S0), 1e-6f);
+      lo = S0 - step;
+      for (int i = 0; i < 160; ++i) {
+        float Fl, dl;
+        lo = S0 - step;
+        F_eval(lo, L, c, G, Fl, dl);
+        if (Fl == 0.f) return lo;
+        if (Fl > 0.f) break;
+        hi = lo;
+        Fhi = Fl;
+        dhi = dl;
+        step *= 2.f;
+      }
+    }
+    S = hi;
+    Fs = Fhi;
+    dFs = dhi;
+  }
+  for (int it = 0; it < 64; ++it) {
+    float Sn = 0.f;
+    bool newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.f;
+    if (newton) {
+      Sn = S - Fs / dFs;
+      newton = (Sn > lo && Sn < hi);
+    }
+    if (!newton) Sn = 0.5f * (lo + hi);
+    float Fn, dn;
+    F_eval(Sn, L, c, G, Fn, dn);
+    ++*steps;
+    if (Fn == 0.f) return Sn;
+    if (Fn > 0.f) lo = Sn; else hi = Sn;
+    float tol = 2.4e-7f * fmaxf(fabsf(Sn), 1e-30f);
+    if (hi - lo <= tol) return Sn;
+    if (newton && fabsf(Sn - S) <= tol) return Sn;
+    S = Sn;
+    Fs = Fn;
+    dFs = dn;
+  }
+  return S;
+}
+
+// ------------------------------------------------------------------------------------------
+// Control decision after iteration k (sections 3.4): residual balancing of beta with
+// rescale of the scaled duals, alpha-increments, stop test.  Sums: [s2, r2, cap, dem].
+// ------------------------------------------------------------------------------------------
+__device__ inline Ctrl decide(const Ctrl &prev, const double *sums, const Params &prm) {
+#pragma clang fp contract(off)
+  if (!prev.pending) return prev;
+  Ctrl c = prev;
+  c.pending = 0;
+  double r = sqrt(sums[1]), s = sqrt(sums[0]);
+  c.r = r;
+  c.s = s;
+  c.cap_viol = sums[2];
+  c.dem_viol = sums[3];
+  int kdone = prev.k + 1;
+  const bool replay = prm.sched_beta != nullptr;
+  double f = 1.0;
+  if (replay) {
+    int kk = kdone < prm.sched_len ? kdone : prm.sched_len - 1;
+    double nb = prm.sched_beta[kk];
+    f = nb / prev.beta;
+    c.beta = nb;
+    c.alpha = prm.sched_alpha[kk];
+  } else {
+    if (prm.adapt_beta && (kdone % prm.beta_every) == 0) {
+      if (r > prm.A * s) {
+        if (prev.beta * prm.C <= prm.beta_max) f = prm.C; else c.flags |= F_BETA_BOUND;
+      } else if (s > prm.A * r) {
+        if (prev.beta / prm.C >= prm.beta_min) f = 1.0 / prm.C; else c.flags |= F_BETA_BOUND;
+      }
+    }
+    c.beta = prev.beta * f;
+    int j = prev.j + 1;
+    bool stop = false;
+    if (r <= prm.gamma && s <= prm.gamma) {
+      bool would_stop = (prev.alpha >= prm.alpha_target) || (prev.alpha >= 1.0 && j <= 1);
+      if (would_stop) {
+        c.flags |= F_CONVERGED;
+        if (c.stop_iter < 0) c.stop_iter = kdone;
+        if (!prm.fixed) stop = true;
+      }
+      if (!stop && prev.alpha < prm.alpha_target) {
+        double na = prev.alpha + 1.0;
+        if (na > prm.alpha_target) na = prm.alpha_target;
+        if (na > (double)prm.alpha_max) {
+          c.flags |= F_ALPHA_MAX;
+          if (!prm.fixed) stop = true;
+        } else {
+          c.alpha = na;
+          j = 0;
+        }
+      }
+    }
+    c.j = j;
+    if (stop) c.stop = 1;
+  }
+  c.inv_f = 1.0 / f;
+  c.k = kdone;
+  if (kdone >= prm.kmax) {
+    if (!c.stop && !prm.fixed && !replay) c.flags |= F_MAX_ITERS;
+    c.stop = 1;
+  }
+  return c;
+}
+
+__device__ inline Ctrl initial_ctrl(const Params &prm) {
+  Ctrl c;
+  const bool replay = prm.sched_beta != nullptr;
+  c.beta = replay ? prm.sched_beta[0] : prm.beta0;
+  c.alpha = replay ? prm.sched_alpha[0] : (prm.alpha_target < 0.0 ? prm.alpha_target : 0.0);
+  c.inv_f = 1.0;
+  c.r = c.s = 0.0;
+  c.cap_viol = c.dem_viol = 0.0;
+  c.k = 0;
+  c.j = 0;
+  c.stop = prm.kmax <= 0;
+  c.flags = 0;
+  c.stop_iter = -1;
+  c.pending = 0;
+  return c;
+}
+
+// 64-bit ordering key of a path in the projection: descending score S_c^alpha * C_p compared
+// through alpha ln S_c + ln C_p, ties broken towards the higher path index.
+__device__ __forceinline__ uint64_t trim_key(float logscore, int32_t p) {
+  uint32_t b = __float_as_uint(logscore);
+  b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);  // order-preserving map of the float
+  return ((uint64_t)b << 32) | (uint32_t)p;
+}
+
+__device__ __forceinline__ float log_score(double S, int Cp, float alpha) {
+  if (Cp <= 0 || !(S > 0.0)) return -INFINITY;
+  return alpha * logf((float)S) + logf((float)Cp);
+}
+
+}  // namespace te

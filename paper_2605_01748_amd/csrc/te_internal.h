@@ -1,0 +1,99 @@
+// te_internal.h -- structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace te {
+
+// Control record of one iteration: the penalty, alpha and stop state that
+// Algorithm 1 (section 3.3) carries from one iteration to the next.
+// Slot (k & 1) holds the record of iteration k; `pending` = 1 means the
+// residual-balancing / alpha / stop decision taken after iteration k has not
+// been applied yet (it is applied redundantly, and identically, by every
+// workgroup that reads the record).
+struct Ctrl {
+  double beta;   // penalty used in iteration k
+  double alpha;  // alpha used in iteration k
+  double inv_f;  // 1/f: rescale of the scaled duals decided after iteration k-1
+  double r, s;   // residuals of iteration k-1
+  double cap_viol, dem_viol;  // max relative violations seen in iteration k-1
+  int32_t k;          // iteration index
+  int32_t j;          // iterations since the last alpha increment
+  int32_t stop;       // 1: no further iterations
+  int32_t flags;      // TE_* flags
+  int32_t stop_iter;  // first iteration whose stop test passed (-1 none)
+  int32_t pending;
+};
+
+// Constant parameters of one solve.
+struct Params {
+  double alpha_target, gamma, A, C, beta_min, beta_max, beta0;
+  int32_t kmax;        // iteration cap
+  int32_t fixed;       // 1: fixed iteration count, no stop
+  int32_t adapt_beta, beta_every, alpha_max;
+  int32_t sched_len;
+  const double *sched_beta;   // device, nullable
+  const double *sched_alpha;  // device, nullable
+};
+
+// Problem arrays on the device (normalised units).
+struct Prob {
+  int32_t E, P, D, nnz;
+  int32_t G, logG;         // lanes per demand (power of two >= max paths per demand)
+  const int32_t *pptr;     // [P+1] path -> incidence range
+  const int32_t *plinks;   // [nnz] link of each incidence (path-major)
+  const int32_t *dptr;     // [D+1] demand -> path range
+  const int32_t *lptr;     // [E+1] link -> CSC range
+  const int32_t *lpaths;   // [nnz] path of each CSC entry (link-major, path-ascending)
+  const float *Dn;         // [D] demand
+  const double *Cn;        // [E] capacity
+};
+
+// Iteration state on the device.
+struct State {
+  float *x, *uneg;   // [P] path rates and non-negativity duals
+  float *udem, *S;   // [D] demand duals and last root of the sum equation
+  float2 *gq;        // [E] (g, q): g = capacity / consensus dual, q = consensus offset
+  Ctrl *ctrl;        // [2]
+  double *partA;     // [2][nA][4]
+  double *partB;     // [2][nB][4]
+  int32_t nA, nB;
+};
+
+constexpr int kLinkBlocks = 128;     // workgroups of the link kernel (partB rows)
+constexpr int kThreads = 256;        // threads per workgroup of the graph-engine kernels
+constexpr int kBlockThreads = 1024;  // threads of the workgroup engine
+
+// Workgroup-engine instance descriptor: offsets into concatenated arrays.
+struct BatchDesc {
+  int32_t E, P, D, nnz, G, logG;
+  int64_t off_pptr, off_plinks, off_dptr, off_lptr, off_lpaths;  // into int32 pools
+  int64_t off_E, off_P, off_D;  // element offsets of per-link / per-path / per-demand arrays
+  double scale;
+};
+
+// Scratch of the graph-engine projection (Algorithm 2).
+struct ProjBuf {
+  double *xd;      // [P] working rates
+  double *S;       // [D]
+  double *L;       // [E]
+  int32_t *Cp;     // [P] violated links per path
+  float *lsc;      // [P] log score
+  uint64_t *trim;  // [P] largest trim (double bits)
+};
+
+// Concatenated inputs of the workgroup engine.
+struct Pools {
+  const int32_t *i32;  // index pool
+  const float *Dn;     // [sum D]
+  const double *Cn;    // [sum E]
+  const float *x0;     // nullable [sum P] warm start, caller units
+};
+
+struct BatchOut {
+  double beta, alpha, r, s, cap_viol, dem_viol;
+  int32_t iters, flags, stop_iter, pad;
+};
+
+}  // namespace te

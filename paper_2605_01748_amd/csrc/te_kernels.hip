@@ -1,0 +1,708 @@
+// te_kernels.hip -- gfx950 kernels of the GATE iteration (section 3.3, Algorithm 1) and of the
+// feasibility projection (section 3.5, Algorithm 2).
+//
+// Graph engine (large instances): one iteration = two device-wide kernels,
+//   k_demand: per demand (G lanes, one per path): gather of (g_e, q_e) along each path,
+//             sum equation by Newton-bisection, rate update, u_dem / u_neg updates;
+//   k_link:   per link (one wavefront): segmented sum of the new rates over the link's CSC
+//             list in FP64, capacity/consensus dual update.
+// Both kernels first apply the control decision of the previous iteration (residual balancing,
+// alpha step, stop) redundantly in every workgroup from the previous iteration's partial sums,
+// so no extra launch or grid-wide barrier is needed; iterations are replayed from a HIP graph.
+//
+// Workgroup engine (small instances, batches): one workgroup runs the whole solve with the
+// instance resident in LDS and __syncthreads() between the steps.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "te_device.h"
+#include "te_internal.h"
+
+namespace te {
+
+// ------------------------------------------------------------------------------------------
+// control record of this iteration, identical in every workgroup
+// ------------------------------------------------------------------------------------------
+__device__ void current_ctrl(const State &s, const Params &prm, int par, Ctrl *out) {
+  // par = k & 1 of this iteration; the record of iteration k-1 and its partial sums live in slot par^1
+  if (threadIdx.x < 64) {
+    const Ctrl prev = s.ctrl[par ^ 1];
+    double v[4] = {0.0, 0.0, 0.0, -INFINITY};
+    v[2] = -INFINITY;
+    if (prev.pending) {
+      const double *pb = s.partB + (size_t)(par ^ 1) * s.nB * 4;
+      for (int i = threadIdx.x; i < s.nB; i += 64) {
+        v[0] += pb[4 * i + 0];
+        v[1] += pb[4 * i + 1];
+        v[2] = fmax(v[2], pb[4 * i + 2]);
+        v[3] = fmax(v[3], pb[4 * i + 3]);
+      }
+      v[0] = wave_sum_d(v[0]);
+      v[1] = wave_sum_d(v[1]);
+      v[2] = wave_max_d(v[2]);
+      v[3] = wave_max_d(v[3]);
+    }
+    if (threadIdx.x == 0) *out = decide(prev, v, prm);
+  }
+  __syncthreads();
+}
+
+// block-wide reduction of 4 partials (sum, sum, max, max) into dst[0..3] by thread 0
+__device__ void block_partials(double p0, double p1, double p2, double p3, double *dst) {
+  __shared__ double red[4][16];
+  p0 = wave_sum_d(p0);
+  p1 = wave_sum_d(p1);
+  p2 = wave_max_d(p2);
+  p3 = wave_max_d(p3);
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][w] = p0;
+    red[1][w] = p1;
+    red[2][w] = p2;
+    red[3][w] = p3;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0, c = -INFINITY, d = -INFINITY;
+    for (int i = 0; i < nw; ++i) {
+      a += red[0][i];
+      b += red[1][i];
+      c = fmax(c, red[2][i]);
+      d = fmax(d, red[3][i]);
+    }
+    dst[0] = a;
+    dst[1] = b;
+    dst[2] = c;
+    dst[3] = d;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Initialisation (Algorithm 1): x^0 = D_c / |P_c| or the warm start, duals zero, y^0 = x^0.
+// ------------------------------------------------------------------------------------------
+__global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, float inv_scale) {
+  const Params &prm = *prmp;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    const int r0 = p.dptr[c], r1 = p.dptr[c + 1];
+    float sum = 0.f;
+    for (int r = r0; r < r1; ++r) {
+      float v = x0 ? x0[r] * inv_scale : p.Dn[c] / (float)(r1 - r0);
+      s.x[r] = v;
+      s.uneg[r] = 0.f;
+      sum += v;
+    }
+    s.udem[c] = 0.f;
+    s.S[c] = sum;
+  }
+  for (int e = tid; e < p.E; e += nth) s.gq[e] = make_float2(0.f, 0.f);
+  if (tid == 0) {
+    Ctrl c = initial_ctrl(prm);
+    s.ctrl[1] = c;   // read as "iteration -1" by iteration 0, not pending
+    s.ctrl[0] = c;
+    s.ctrl[2] = c;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Step a1 + a2: gather along paths, per-demand Newton-bisection, rate and dual updates.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Params *prmp, int par) {
+  const Params &prm = *prmp;
+  __shared__ Ctrl cs;
+  current_ctrl(s, prm, par, &cs);
+  if (cs.stop) return;
+  const float inv_f = (float)cs.inv_f;
+  const int G = p.G;
+  const int t = threadIdx.x;
+  const int lane = t & (G - 1);
+  const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
+  double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
+  if (c < p.D) {
+    const int r0 = p.dptr[c], np = p.dptr[c + 1] - r0;
+    Lane L;
+    L.on = lane < np;
+    const int r = r0 + (L.on ? lane : 0);
+    float xr = 0.f;
+    int n = 1;
+    L.a = 0.f;
+    L.un = 0.f;
+    if (L.on) {
+      const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
+      n = i1 - i0;
+      float G_r = 0.f;
+      for (int i = i0; i < i1; ++i) {
+        const float2 v = s.gq[p.plinks[i]];
+        G_r += v.x * inv_f - v.y;
+      }
+      xr = s.x[r];
+      L.a = (float)n * xr - G_r;
+      L.un = s.uneg[r] * inv_f;
+    }
+    L.n = (float)n;
+    L.rn = 1.f / (float)n;
+    L.rn1 = 1.f / (float)(n + 1);
+    Dem dm;
+    dm.D = p.Dn[c];
+    dm.u = s.udem[c] * inv_f;
+    dm.alpha = (float)cs.alpha;
+    dm.binv = (float)(1.0 / cs.beta);
+    int steps;
+    const float Sst = sum_root(s.S[c], L, dm, G, &steps);
+    const float h = h_of(Sst, dm);
+    const float xn = L.on ? xi_of(L.a - h, L) : 0.f;
+    const float Ssum = group_sum(xn, G);
+    if (L.on) {
+      const float un = fmaxf(L.un - xn, 0.f);
+      s.x[r] = xn;
+      s.uneg[r] = un;
+      ds2 = (double)(xn - xr) * (double)(xn - xr);
+      dr2 = (double)(un - L.un) * (double)(un - L.un);
+    }
+    if (lane == 0) {
+      const float ud = fmaxf(dm.u + Ssum - dm.D, 0.f);
+      s.udem[c] = ud;
+      s.S[c] = Sst;
+      dr2 += (double)(ud - dm.u) * (double)(ud - dm.u);
+      dem_v = ((double)Ssum - (double)dm.D) / (double)dm.D;
+    }
+  }
+  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
+}
+
+// ------------------------------------------------------------------------------------------
+// Step a3 + a4: link loads by segmented FP64 sums over the CSC lists, capacity/consensus duals.
+// Also folds a slice of the demand kernel's partial sums into this workgroup's row.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_link(Prob p, State s, const Params *prmp, int par) {
+  const Params &prm = *prmp;
+  __shared__ Ctrl cs;
+  current_ctrl(s, prm, par, &cs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    Ctrl w = cs;
+    w.pending = cs.stop ? 0 : 1;
+    s.ctrl[par] = w;
+  }
+  if (cs.stop) return;
+  const double inv_f = cs.inv_f;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  double dr2 = 0.0, cap_v = -INFINITY;
+  for (int e = blockIdx.x * nw + w; e < p.E; e += gridDim.x * nw) {
+    const int j0 = p.lptr[e], j1 = p.lptr[e + 1];
+    double acc = 0.0;
+    for (int j = j0 + lane; j < j1; j += 64) acc += (double)s.x[p.lpaths[j]];
+    acc = wave_sum_d(acc);
+    if (lane == 0) {
+      const float2 v = s.gq[e];
+      const float gold = (float)((double)v.x * inv_f);
+      const int ne = j1 - j0;
+      const double Ce = p.Cn[e];
+      double g = (double)gold + (acc - Ce) / (double)(1 + ne);
+      const float gn = (float)fmax(g, 0.0);
+      s.gq[e] = make_float2(gn, gold - gn);
+      dr2 += (double)(1 + ne) * (double)(gn - gold) * (double)(gn - gold);
+      if (ne > 0) cap_v = fmax(cap_v, (acc - Ce) / Ce);
+    }
+  }
+  // fold the demand kernel's rows b, b + nB, ... (fixed order)
+  double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
+  if (w == 0) {
+    const double *pa = s.partA + (size_t)par * s.nA * 4;
+    for (int i = blockIdx.x + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
+      a0 += pa[4 * i + 0];
+      a1 += pa[4 * i + 1];
+      a3 = fmax(a3, pa[4 * i + 3]);
+    }
+  }
+  block_partials(a0, dr2 + a1, cap_v, a3, s.partB + ((size_t)par * s.nB + blockIdx.x) * 4);
+}
+
+// Final control record: applies the decision pending after the last iteration.
+__global__ void k_finish(State s, const Params *prmp, int last_par) {
+  const Params &prm = *prmp;
+  if (threadIdx.x < 64) {
+    const Ctrl prev = s.ctrl[last_par];
+    double v[4] = {0.0, 0.0, -INFINITY, -INFINITY};
+    if (prev.pending) {
+      const double *pb = s.partB + (size_t)last_par * s.nB * 4;
+      for (int i = threadIdx.x; i < s.nB; i += 64) {
+        v[0] += pb[4 * i + 0];
+        v[1] += pb[4 * i + 1];
+        v[2] = fmax(v[2], pb[4 * i + 2]);
+        v[3] = fmax(v[3], pb[4 * i + 3]);
+      }
+      v[0] = wave_sum_d(v[0]);
+      v[1] = wave_sum_d(v[1]);
+      v[2] = wave_max_d(v[2]);
+      v[3] = wave_max_d(v[3]);
+    }
+    if (threadIdx.x == 0) s.ctrl[2] = decide(prev, v, prm);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Algorithm 2 on the graph engine.  FP64 loads and trims; final rates rounded toward zero.
+// ------------------------------------------------------------------------------------------
+// clamp at zero (step 1) and demand sums
+__global__ void kp_clamp_sums(Prob p, State s, ProjBuf b) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    double sum = 0.0;
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      const double v = fmax((double)s.x[r], 0.0);
+      b.xd[r] = v;
+      sum += v;
+      b.trim[r] = 0ull;
+    }
+    b.S[c] = sum;
+  }
+}
+
+__global__ void kp_loads(Prob p, ProjBuf b) {
+  const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int e = w; e < p.E; e += nw) {
+    double acc = 0.0;
+    for (int j = p.lptr[e] + lane; j < p.lptr[e + 1]; j += 64) acc += b.xd[p.lpaths[j]];
+    acc = wave_sum_d(acc);
+    if (lane == 0) b.L[e] = acc;
+  }
+}
+
+// C_p = number of violated links on p, and the log score
+__global__ void kp_counts(Prob p, ProjBuf b, const Ctrl *fin) {
+  const float alpha = (float)fin->alpha;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      int k = 0;
+      for (int i = p.pptr[r]; i < p.pptr[r + 1]; ++i) {
+        const int e = p.plinks[i];
+        k += b.L[e] > p.Cn[e];
+      }
+      b.Cp[r] = k;
+      b.lsc[r] = log_score(b.S[c], k, alpha);
+    }
+  }
+}
+
+// step 3: per demand, trim the excess over D_c from paths in descending score
+// (S_c is common to the demand's paths: the order is by C_p, ties to the higher index)
+__global__ void kp_demand_trim(Prob p, ProjBuf b) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    double excess = b.S[c] - (double)p.Dn[c];
+    if (!(excess > 0.0)) continue;
+    const int r0 = p.dptr[c], r1 = p.dptr[c + 1];
+    // selection by repeated arg-max over at most 64 paths
+    uint64_t done = 0ull;
+    for (int it = 0; it < r1 - r0 && excess > 0.0; ++it) {
+      int best = -1;
+      for (int r = r0; r < r1; ++r) {
+        if (done >> (r - r0) & 1ull) continue;
+        if (best < 0 || trim_key(b.lsc[r], r) > trim_key(b.lsc[best], best)) best = r;
+      }
+      done |= 1ull << (best - r0);
+      const double d = fmin(excess, b.xd[best]);
+      b.xd[best] -= d;
+      excess -= d;
+    }
+    double sum = 0.0;
+    for (int r = r0; r < r1; ++r) sum += b.xd[r];
+    b.S[c] = sum;
+  }
+}
+
+// step 5: one workgroup per link; every link trims from the same snapshot: the paths above
+// the threshold key K* (the key at which the descending cumulative rate reaches V_e) give up
+// all their rate, the path at K* the remainder; a path trimmed by several links keeps the max.
+__global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
+  __shared__ double red[4];
+  __shared__ uint64_t keyT;
+  for (int e = blockIdx.x; e < p.E; e += gridDim.x) {
+    const double V = b.L[e] - p.Cn[e];
+    if (!(V > 0.0)) continue;  // uniform in the workgroup
+    const int j0 = p.lptr[e], j1 = p.lptr[e + 1];
+    // f(T) = sum of x over incidences with key >= T; find the largest T with f(T) >= V
+    uint64_t lo = 0ull, hi = ~0ull;  // invariant: f(lo) >= V, f(hi + 1) < V region search
+    // binary search on [lo, hi]
+    for (int bit = 0; bit < 64; ++bit) {
+      const uint64_t mid = lo + ((hi - lo) >> 1) + ((hi - lo) & 1ull);
+      double acc = 0.0;
+      for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+        const int r = p.lpaths[j];
+        if (trim_key(b.lsc[r], r) >= mid) acc += b.xd[r];
+      }
+      acc = wave_sum_d(acc);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      __syncthreads();
+      const double f = red[0] + red[1] + red[2] + red[3];
+      __syncthreads();
+      if (f >= V) lo = mid; else hi = mid - 1;
+      if (lo >= hi) break;
+    }
+    if (threadIdx.x == 0) keyT = lo;
+    __syncthreads();
+    const uint64_t T = keyT;
+    // rate strictly above the threshold key
+    double acc = 0.0;
+    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      const int r = p.lpaths[j];
+      if (trim_key(b.lsc[r], r) > T) acc += b.xd[r];
+    }
+    acc = wave_sum_d(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    const double above = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      const int r = p.lpaths[j];
+      const uint64_t k = trim_key(b.lsc[r], r);
+      double d = 0.0;
+      if (k > T) d = b.xd[r];
+      else if (k == T) d = fmin(b.xd[r], fmax(V - above, 0.0));
+      if (d > 0.0) atomicMax((unsigned long long *)&b.trim[r], (unsigned long long)__double_as_longlong(d));
+    }
+    __syncthreads();
+  }
+}
+
+// step 6 and outputs in caller units (rounded toward zero: the FP32 rates stay feasible)
+__global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double scale, int project, const float *xs) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    double sum = 0.0;
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      double v;
+      if (project) {
+        v = b.xd[r] - __longlong_as_double((long long)b.trim[r]);
+        v = fmax(v, 0.0) * scale;
+        x_out[r] = __double2float_rz(v);
+      } else {
+        v = (double)xs[r] * scale;
+        x_out[r] = (float)v;
+      }
+      sum += (double)x_out[r];
+    }
+    if (S_out) S_out[c] = (float)sum;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Workgroup engine: the whole solve of one instance inside one workgroup, state in LDS.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *descs, Pools pools,
+                                                               const Params *prmp, int project, float *x_out,
+                                                               float *S_out, BatchOut *outs) {
+  const Params &prm = *prmp;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ Ctrl cs;
+  __shared__ double red[4][16];
+  const BatchDesc d = descs[blockIdx.x];
+  const int E = d.E, P = d.P, D = d.D, nnz = d.nnz, G = d.G, logG = d.logG;
+  // LDS layout
+  double *Cn = (double *)smem;                       // E
+  double *Lx = Cn + E;                               // E  (loads, FP64)
+  float2 *gq = (float2 *)(Lx + E);                   // E
+  float *x = (float *)(gq + E);                      // P
+  float *uneg = x + P;                               // P
+  float *udem = uneg + P;                            // D
+  float *S = udem + D;                               // D
+  float *Dn = S + D;                                 // D
+  int32_t *pptr = (int32_t *)(Dn + D);               // P + 1
+  int32_t *plinks = pptr + P + 1;                    // nnz
+  int32_t *dptr = plinks + nnz;                      // D + 1
+  int32_t *lptr = dptr + D + 1;                      // E + 1
+  int32_t *lpaths = lptr + E + 1;                    // nnz
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int32_t *gi = pools.i32;
+  for (int i = tid; i <= P; i += nth) pptr[i] = gi[d.off_pptr + i];
+  for (int i = tid; i < nnz; i += nth) plinks[i] = gi[d.off_plinks + i];
+  for (int i = tid; i <= D; i += nth) dptr[i] = gi[d.off_dptr + i];
+  for (int i = tid; i <= E; i += nth) lptr[i] = gi[d.off_lptr + i];
+  for (int i = tid; i < nnz; i += nth) lpaths[i] = gi[d.off_lpaths + i];
+  for (int i = tid; i < E; i += nth) {
+    Cn[i] = pools.Cn[d.off_E + i];
+    gq[i] = make_float2(0.f, 0.f);
+  }
+  for (int i = tid; i < D; i += nth) Dn[i] = pools.Dn[d.off_D + i];
+  __syncthreads();
+  const float inv_scale = (float)(1.0 / d.scale);
+  for (int c = tid; c < D; c += nth) {
+    const int r0 = dptr[c], r1 = dptr[c + 1];
+    float sum = 0.f;
+    for (int r = r0; r < r1; ++r) {
+      const float v = pools.x0 ? pools.x0[d.off_P + r] * inv_scale : Dn[c] / (float)(r1 - r0);
+      x[r] = v;
+      uneg[r] = 0.f;
+      sum += v;
+    }
+    udem[c] = 0.f;
+    S[c] = sum;
+  }
+  if (tid == 0) cs = initial_ctrl(prm);
+  __syncthreads();
+
+  const int lane = tid & (G - 1);
+  const int groups = nth >> logG;
+  const int w = tid >> 6, l64 = tid & 63, nw = nth >> 6;
+  while (!cs.stop) {
+    const float inv_f = (float)cs.inv_f;
+    Dem dm;
+    dm.alpha = (float)cs.alpha;
+    dm.binv = (float)(1.0 / cs.beta);
+    double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY, cap_v = -INFINITY;
+    // demand step
+    for (int c0 = 0; c0 < D; c0 += groups) {
+      const int c = c0 + (tid >> logG);
+      if (c < D) {
+        const int r0 = dptr[c], np = dptr[c + 1] - r0;
+        Lane L;
+        L.on = lane < np;
+        const int r = r0 + (L.on ? lane : 0);
+        float xr = 0.f;
+        int n = 1;
+        L.a = 0.f;
+        L.un = 0.f;
+        if (L.on) {
+          const int i0 = pptr[r], i1 = pptr[r + 1];
+          n = i1 - i0;
+          float G_r = 0.f;
+          for (int i = i0; i < i1; ++i) {
+            const float2 v = gq[plinks[i]];
+            G_r += v.x * inv_f - v.y;
+          }
+          xr = x[r];
+          L.a = (float)n * xr - G_r;
+          L.un = uneg[r] * inv_f;
+        }
+        L.n = (float)n;
+        L.rn = 1.f / (float)n;
+        L.rn1 = 1.f / (float)(n + 1);
+        dm.D = Dn[c];
+        dm.u = udem[c] * inv_f;
+        int steps;
+        const float Sst = sum_root(S[c], L, dm, G, &steps);
+        const float h = h_of(Sst, dm);
+        const float xn = L.on ? xi_of(L.a - h, L) : 0.f;
+        const float Ssum = group_sum(xn, G);
+        if (L.on) {
+          const float un = fmaxf(L.un - xn, 0.f);
+          x[r] = xn;
+          uneg[r] = un;
+          ds2 += (double)(xn - xr) * (double)(xn - xr);
+          dr2 += (double)(un - L.un) * (double)(un - L.un);
+        }
+        if (lane == 0) {
+          const float ud = fmaxf(dm.u + Ssum - dm.D, 0.f);
+          udem[c] = ud;
+          S[c] = Sst;
+          dr2 += (double)(ud - dm.u) * (double)(ud - dm.u);
+          dem_v = fmax(dem_v, ((double)Ssum - (double)dm.D) / (double)dm.D);
+        }
+      }
+    }
+    __syncthreads();
+    // link step
+    for (int e = w; e < E; e += nw) {
+      const int j0 = lptr[e], j1 = lptr[e + 1];
+      double acc = 0.0;
+      for (int j = j0 + l64; j < j1; j += 64) acc += (double)x[lpaths[j]];
+      acc = wave_sum_d(acc);
+      if (l64 == 0) {
+        const float2 v = gq[e];
+        const float gold = (float)((double)v.x * (double)cs.inv_f);
+        const int ne = j1 - j0;
+        const double g = (double)gold + (acc - Cn[e]) / (double)(1 + ne);
+        const float gn = (float)fmax(g, 0.0);
+        gq[e] = make_float2(gn, gold - gn);
+        dr2 += (double)(1 + ne) * (double)(gn - gold) * (double)(gn - gold);
+        if (ne > 0) cap_v = fmax(cap_v, (acc - Cn[e]) / Cn[e]);
+      }
+    }
+    // partial sums and decision
+    ds2 = wave_sum_d(ds2);
+    dr2 = wave_sum_d(dr2);
+    cap_v = wave_max_d(cap_v);
+    dem_v = wave_max_d(dem_v);
+    if (l64 == 0) {
+      red[0][w] = ds2;
+      red[1][w] = dr2;
+      red[2][w] = cap_v;
+      red[3][w] = dem_v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v[4] = {0.0, 0.0, -INFINITY, -INFINITY};
+      for (int i = 0; i < nw; ++i) {
+        v[0] += red[0][i];
+        v[1] += red[1][i];
+        v[2] = fmax(v[2], red[2][i]);
+        v[3] = fmax(v[3], red[3][i]);
+      }
+      Ctrl c = cs;
+      c.pending = 1;
+      cs = decide(c, v, prm);
+    }
+    __syncthreads();
+  }
+
+  // ---------------- Algorithm 2 (if requested) ----------------
+  // x (LDS) holds the working rates; per-path log scores go to uneg; per-path trims of the
+  // link phase are combined by max in x_out (float bits of non-negative values).
+  const float alpha = (float)cs.alpha;
+  float *xo = x_out + d.off_P;
+  for (int r = tid; r < P; r += nth) xo[r] = 0.f;
+  if (project) {
+    for (int r = tid; r < P; r += nth) x[r] = fmaxf(x[r], 0.f);
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int e = w; e < E; e += nw) {
+        double acc = 0.0;
+        for (int j = lptr[e] + l64; j < lptr[e + 1]; j += 64) acc += (double)x[lpaths[j]];
+        acc = wave_sum_d(acc);
+        if (l64 == 0) Lx[e] = acc;
+      }
+      __syncthreads();
+      for (int c = tid; c < D; c += nth) {
+        double sum = 0.0;
+        for (int r = dptr[c]; r < dptr[c + 1]; ++r) sum += (double)x[r];
+        for (int r = dptr[c]; r < dptr[c + 1]; ++r) {
+          int k = 0;
+          for (int i = pptr[r]; i < pptr[r + 1]; ++i) k += Lx[plinks[i]] > Cn[plinks[i]];
+          uneg[r] = log_score(sum, k, alpha);
+        }
+        if (pass == 0) {
+          // demand phase: trim the excess over D_c in descending score
+          const int r0 = dptr[c], r1 = dptr[c + 1];
+          double excess = sum - (double)Dn[c];
+          uint64_t done = 0ull;
+          for (int it = 0; it < r1 - r0 && excess > 0.0; ++it) {
+            int best = -1;
+            for (int r = r0; r < r1; ++r) {
+              if (done >> (r - r0) & 1ull) continue;
+              if (best < 0 || trim_key(uneg[r], r) > trim_key(uneg[best], best)) best = r;
+            }
+            done |= 1ull << (best - r0);
+            const double dd = fmin(excess, (double)x[best]);
+            x[best] = __double2float_rz((double)x[best] - dd);
+            excess -= dd;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // link phase: every violated link trims from the same snapshot, one wavefront per link,
+    // X_before(p) = rate of the link's paths with a larger key; a path keeps the largest trim
+    for (int e = w; e < E; e += nw) {
+      const double V = Lx[e] - Cn[e];
+      if (!(V > 0.0)) continue;
+      const int j0 = lptr[e], j1 = lptr[e + 1];
+      for (int j = j0 + l64; j < j1; j += 64) {
+        const int r = lpaths[j];
+        const uint64_t kr = trim_key(uneg[r], r);
+        double before = 0.0;
+        for (int i = j0; i < j1; ++i) {
+          const int q = lpaths[i];
+          if (trim_key(uneg[q], q) > kr) before += (double)x[q];
+        }
+        const double dd = fmin((double)x[r], fmax(V - before, 0.0));
+        if (dd > 0.0) atomicMax((unsigned int *)&xo[r], __float_as_uint((float)dd));
+      }
+    }
+  }
+  __syncthreads();
+  // outputs: x_out holds the per-path trims (float bits, non-negative) when projecting
+  const double scale = d.scale;
+  for (int c = tid; c < D; c += nth) {
+    double sum = 0.0;
+    for (int r = dptr[c]; r < dptr[c + 1]; ++r) {
+      double v = (double)x[r];
+      if (project) v = fmax(v - (double)xo[r], 0.0);
+      const float o = project ? __double2float_rz(v * scale) : (float)(v * scale);
+      xo[r] = o;
+      sum += (double)o;
+    }
+    if (S_out) S_out[d.off_D + c] = (float)sum;
+  }
+  if (tid == 0) {
+    BatchOut o;
+    o.beta = cs.beta;
+    o.alpha = cs.alpha;
+    o.r = cs.r;
+    o.s = cs.s;
+    o.cap_viol = cs.cap_viol;
+    o.dem_viol = cs.dem_viol;
+    o.iters = cs.k;
+    o.flags = cs.flags;
+    o.stop_iter = cs.stop_iter;
+    o.pad = 0;
+    outs[blockIdx.x] = o;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host-side launchers
+// ------------------------------------------------------------------------------------------
+hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const float *x0, float inv_scale,
+                       hipStream_t st) {
+  int n = p.D > p.E ? p.D : p.E;
+  int blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, st, p, s, prm, x0, inv_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
+  hipLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
+  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kThreads), 0, st, p, s, prm, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const State &s, const Params *prm, int last_par, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, s, prm, last_par);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const Prob &p, const State &s, const ProjBuf &b, float *x_out, float *S_out,
+                          double scale, int project, hipStream_t st) {
+  const Ctrl *fin = s.ctrl + 2;
+  const int nD = (p.D + 255) / 256, nE = (p.E * 64 + 255) / 256;
+  if (project) {
+    hipLaunchKernelGGL(kp_clamp_sums, dim3(nD), dim3(256), 0, st, p, s, b);
+    hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
+    hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin);
+    hipLaunchKernelGGL(kp_demand_trim, dim3(nD), dim3(256), 0, st, p, b);
+    hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
+    hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin);
+    int nl = p.E < 4096 ? p.E : 4096;
+    hipLaunchKernelGGL(kp_link_trim, dim3(nl > 0 ? nl : 1), dim3(256), 0, st, p, b);
+  }
+  hipLaunchKernelGGL(kp_output, dim3(nD), dim3(256), 0, st, p, b, x_out, S_out, scale, project, s.x);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
+                              float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_block_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_solve, dim3(n), dim3(kBlockThreads), lds_bytes, st, descs, pools, prm, project, x_out,
+                     S_out, outs);
+  return hipGetLastError();
+}
+
+size_t block_lds_bytes(int E, int P, int D, int nnz) {
+  return (size_t)E * (8 + 8 + 8) + (size_t)P * 4 * 2 + (size_t)D * 4 * 3 +
+         (size_t)4 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz) + 16;
+}
+
+}  // namespace te

@@ -1,0 +1,679 @@
+// te_runtime.cpp -- host side of the C ABI declared in include/te.h.
+//
+// Builds the device layout of an instance (path -> link CSR, link -> path CSC, demand -> path
+// ranges, normalised capacities and demands), owns the device state, drives the iterations of
+// the graph engine as captured HIP graphs of fixed-length iteration chunks, and runs the
+// workgroup engine for small instances and batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/te.h"
+#include "te_internal.h"
+
+namespace te {
+hipError_t launch_init(const Prob &, const State &, const Params *, const float *, float, hipStream_t);
+hipError_t launch_iteration(const Prob &, const State &, const Params *, int, hipStream_t);
+hipError_t launch_finish(const State &, const Params *, int, hipStream_t);
+hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *, float *, double, int, hipStream_t);
+hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
+                              BatchOut *, size_t, hipStream_t);
+size_t block_lds_bytes(int E, int P, int D, int nnz);
+}  // namespace te
+
+using namespace te;
+
+namespace {
+
+thread_local std::string g_err;
+
+te_status fail(te_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(TE_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kChunk = 16;                 // iterations per captured graph (even)
+constexpr size_t kMaxBlockLds = 160 * 1024 - 4096;
+
+template <class T>
+hipError_t dalloc(T **p, size_t n) {
+  return hipMalloc((void **)p, sizeof(T) * (n ? n : 1));
+}
+
+}  // namespace
+
+struct te_ctx {
+  int device = 0;
+  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0;
+  double scale = 1.0;
+  // host layout (kept for batches and updates)
+  std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
+  std::vector<double> cap, dem;  // caller units
+  std::vector<float> Dn;
+  std::vector<double> Cn;
+  // device
+  Prob prob{};
+  State st{};
+  ProjBuf pb{};
+  Params *d_params = nullptr;
+  Params *h_params = nullptr;  // pinned staging
+  hipEvent_t params_ev = nullptr;
+  double *d_sched = nullptr;
+  int32_t sched_cap = 0;
+  int32_t *d_i32 = nullptr;
+  float *d_Dn = nullptr;
+  double *d_Cn = nullptr;
+  // workgroup engine (single instance)
+  BatchDesc *d_desc = nullptr;
+  BatchOut *d_bout = nullptr;
+  // graph of kChunk iterations
+  hipGraphExec_t chunk = nullptr;
+  int32_t *h_flag = nullptr;  // pinned: stop flags of chunks in flight
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing
+  hipEvent_t pe[2] = {nullptr, nullptr};    // polling of the stop flag
+  size_t lds_bytes = 0;
+};
+
+struct te_batch {
+  int device = 0;
+  int32_t n = 0;
+  std::vector<int32_t> P, D, Eoff;
+  std::vector<BatchDesc> desc;
+  BatchDesc *d_desc = nullptr;
+  BatchOut *d_out = nullptr;
+  int32_t *d_i32 = nullptr;
+  float *d_Dn = nullptr;
+  double *d_Cn = nullptr;
+  Params *d_params = nullptr;
+  Params *h_params = nullptr;
+  hipEvent_t params_ev = nullptr;
+  double *d_sched = nullptr;
+  int32_t sched_cap = 0;
+  size_t lds_bytes = 0;
+  int64_t totP = 0, totD = 0;
+  std::vector<double> scales;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+extern "C" {
+
+const char *te_last_error(void) { return g_err.c_str(); }
+
+void te_default_options(te_options *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->alpha_target = INFINITY;
+  o->gamma = 1e-3;
+  o->beta0 = 1.0;
+  o->A = 10.0;
+  o->C = 2.0;
+  o->beta_min = 1e-3;
+  o->beta_max = 1e3;
+  o->max_iters = 20000;
+  o->alpha_max = 64;
+  o->fixed_iters = 0;
+  o->adapt_beta = 1;
+  o->beta_every = 5;
+  o->project = 1;
+  o->engine = TE_ENGINE_AUTO;
+  o->record = 0;
+  o->ckpt_every = 16;
+  o->sched_beta = nullptr;
+  o->sched_alpha = nullptr;
+  o->sched_len = 0;
+}
+
+te_status te_validate(int32_t n_links, const double *capacity, int32_t n_paths, const int64_t *path_ptr,
+                      const int32_t *path_links, int32_t n_demands, const int32_t *demand_path_ptr,
+                      const double *demand) {
+  if (n_links <= 0 || n_paths <= 0 || n_demands <= 0)
+    return fail(TE_ERR_INVALID, "empty instance (links %d, paths %d, demands %d)", n_links, n_paths, n_demands);
+  if (!capacity || !path_ptr || !path_links || !demand_path_ptr || !demand)
+    return fail(TE_ERR_INVALID, "null input array");
+  if (path_ptr[0] != 0) return fail(TE_ERR_INVALID, "path_ptr[0] must be 0");
+  for (int32_t r = 0; r < n_paths; ++r)
+    if (path_ptr[r + 1] <= path_ptr[r]) return fail(TE_ERR_INVALID, "path %d is empty or path_ptr decreases", r);
+  const int64_t nnz = path_ptr[n_paths];
+  if (nnz >= (int64_t)INT32_MAX) return fail(TE_ERR_INVALID, "too many path-link incidences (%lld)", (long long)nnz);
+  std::vector<int32_t> stamp(n_links, -1);
+  std::vector<char> used(n_links, 0);
+  for (int32_t r = 0; r < n_paths; ++r)
+    for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) {
+      const int32_t e = path_links[i];
+      if (e < 0 || e >= n_links) return fail(TE_ERR_INVALID, "path %d uses link id %d out of range", r, e);
+      if (stamp[e] == r) return fail(TE_ERR_INVALID, "path %d uses link %d twice", r, e);
+      stamp[e] = r;
+      used[e] = 1;
+    }
+  if (demand_path_ptr[0] != 0) return fail(TE_ERR_INVALID, "demand_path_ptr[0] must be 0");
+  if (demand_path_ptr[n_demands] != n_paths)
+    return fail(TE_ERR_INVALID, "demand_path_ptr[n_demands] = %d, expected n_paths = %d", demand_path_ptr[n_demands],
+                n_paths);
+  for (int32_t c = 0; c < n_demands; ++c) {
+    const int32_t m = demand_path_ptr[c + 1] - demand_path_ptr[c];
+    if (m <= 0) return fail(TE_ERR_INVALID, "demand %d has no path", c);
+    if (m > 64) return fail(TE_ERR_INVALID, "demand %d has %d paths (at most 64 supported)", c, m);
+    if (!std::isfinite(demand[c]) || !(demand[c] > 0.0))
+      return fail(TE_ERR_INVALID, "demand %d is %g (must be finite and > 0)", c, demand[c]);
+  }
+  for (int32_t e = 0; e < n_links; ++e) {
+    if (!std::isfinite(capacity[e])) return fail(TE_ERR_INVALID, "capacity of link %d is not finite", e);
+    if (used[e] && !(capacity[e] > 0.0))
+      return fail(TE_ERR_INVALID, "link %d is used by a path but has capacity %g", e, capacity[e]);
+  }
+  return TE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+void normalise(te_ctx *c) {
+  double s = 0.0;
+  for (int32_t i = 0; i < c->nnz; ++i) s = std::max(s, c->cap[c->plinks[i]]);
+  c->scale = s;
+  c->Cn.resize(c->E);
+  c->Dn.resize(c->D);
+  for (int32_t e = 0; e < c->E; ++e) c->Cn[e] = c->cap[e] / s;
+  for (int32_t k = 0; k < c->D; ++k) c->Dn[k] = (float)(c->dem[k] / s);
+}
+
+te_status upload_values(te_ctx *c) {
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(hipMemcpy(c->d_Cn, c->Cn.data(), sizeof(double) * c->E, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_Dn, c->Dn.data(), sizeof(float) * c->D, hipMemcpyHostToDevice));
+  BatchDesc d{};
+  d.E = c->E;
+  d.P = c->P;
+  d.D = c->D;
+  d.nnz = c->nnz;
+  d.G = c->G;
+  d.logG = c->logG;
+  d.off_pptr = 0;
+  d.off_plinks = (int64_t)c->P + 1;
+  d.off_dptr = d.off_plinks + c->nnz;
+  d.off_lptr = d.off_dptr + c->D + 1;
+  d.off_lpaths = d.off_lptr + c->E + 1;
+  d.off_E = d.off_P = d.off_D = 0;
+  d.scale = c->scale;
+  HIPCHK(hipMemcpy(c->d_desc, &d, sizeof(d), hipMemcpyHostToDevice));
+  return TE_OK;
+}
+
+te_status stage_params(Params **d_params, Params *h_params, hipEvent_t ev, double **d_sched, int32_t *sched_cap,
+                       const te_options *o, hipStream_t stream) {
+  HIPCHK(hipEventSynchronize(ev));  // previous staging copy done
+  Params p{};
+  p.alpha_target = o->alpha_target;
+  p.gamma = o->gamma;
+  p.A = o->A;
+  p.C = o->C;
+  p.beta_min = o->beta_min;
+  p.beta_max = o->beta_max;
+  p.beta0 = o->beta0;
+  p.fixed = o->fixed_iters > 0;
+  p.kmax = o->fixed_iters > 0 ? o->fixed_iters : o->max_iters;
+  p.adapt_beta = o->adapt_beta;
+  p.beta_every = o->beta_every > 0 ? o->beta_every : 1;
+  p.alpha_max = o->alpha_max;
+  p.sched_len = 0;
+  p.sched_beta = p.sched_alpha = nullptr;
+  if (o->sched_beta && o->sched_alpha && o->sched_len > 0) {
+    if (*sched_cap < o->sched_len) {
+      if (*d_sched) HIPCHK(hipFree(*d_sched));
+      *d_sched = nullptr;
+      HIPCHK(dalloc(d_sched, 2 * (size_t)o->sched_len));
+      *sched_cap = o->sched_len;
+    }
+    HIPCHK(hipMemcpyAsync(*d_sched, o->sched_beta, sizeof(double) * o->sched_len, hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(*d_sched + o->sched_len, o->sched_alpha, sizeof(double) * o->sched_len,
+                          hipMemcpyHostToDevice, stream));
+    p.sched_len = o->sched_len;
+    p.sched_beta = *d_sched;
+    p.sched_alpha = *d_sched + o->sched_len;
+  }
+  *h_params = p;
+  HIPCHK(hipMemcpyAsync(*d_params, h_params, sizeof(Params), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(ev, stream));
+  return TE_OK;
+}
+
+te_status check_options(const te_options *o) {
+  if (!(o->gamma >= 0.0) || !(o->beta0 > 0.0) || !(o->A > 0.0) || !(o->C > 1.0) || !(o->beta_min > 0.0) ||
+      !(o->beta_max >= o->beta_min) || !(o->alpha_target >= 0.0))
+    return fail(TE_ERR_INVALID, "invalid options (gamma, beta0, A, C, beta bounds or alpha_target)");
+  if (o->fixed_iters <= 0 && o->max_iters <= 0) return fail(TE_ERR_INVALID, "max_iters must be > 0");
+  if (o->sched_len < 0) return fail(TE_ERR_INVALID, "sched_len < 0");
+  return TE_OK;
+}
+
+te_status build_chunk_graph(te_ctx *c, hipStream_t stream) {
+  if (c->chunk) return TE_OK;
+  hipStream_t cap;
+  HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+  for (int i = 0; i < kChunk; ++i) {
+    hipError_t e = launch_iteration(c->prob, c->st, c->d_params, i & 1, cap);
+    if (e != hipSuccess) {
+      hipGraph_t g;
+      (void)hipStreamEndCapture(cap, &g);
+      (void)hipStreamDestroy(cap);
+      return fail(TE_ERR_DEVICE, "iteration launch during capture: %s", hipGetErrorString(e));
+    }
+  }
+  hipGraph_t g;
+  HIPCHK(hipStreamEndCapture(cap, &g));
+  HIPCHK(hipGraphInstantiate(&c->chunk, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphDestroy(g));
+  HIPCHK(hipStreamDestroy(cap));
+  (void)stream;
+  return TE_OK;
+}
+
+void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms) {
+  s->iters = c.k;
+  s->flags = c.flags;
+  s->stop_iter = c.stop_iter;
+  s->engine = engine;
+  s->final_alpha = c.alpha;
+  s->beta = c.beta;
+  s->r = c.r;
+  s->s = c.s;
+  s->max_cap_viol_rel = c.cap_viol;
+  s->max_dem_viol_rel = c.dem_viol;
+  s->ms = ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, const int64_t *path_ptr,
+                    const int32_t *path_links, int32_t n_demands, const int32_t *demand_path_ptr,
+                    const double *demand, int32_t hip_device, te_ctx **out) {
+  if (!out) return fail(TE_ERR_INVALID, "out is null");
+  *out = nullptr;
+  te_status v = te_validate(n_links, capacity, n_paths, path_ptr, path_links, n_demands, demand_path_ptr, demand);
+  if (v != TE_OK) return v;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(TE_ERR_DEVICE, "no HIP device available");
+  if (hip_device < 0 || hip_device >= ndev) return fail(TE_ERR_INVALID, "hip_device %d out of range", hip_device);
+  te_ctx *c = new (std::nothrow) te_ctx();
+  if (!c) return fail(TE_ERR_OOM, "host allocation");
+  c->device = hip_device;
+  c->E = n_links;
+  c->P = n_paths;
+  c->D = n_demands;
+  c->nnz = (int32_t)path_ptr[n_paths];
+  c->cap.assign(capacity, capacity + n_links);
+  c->dem.assign(demand, demand + n_demands);
+  c->pptr.resize(n_paths + 1);
+  for (int32_t r = 0; r <= n_paths; ++r) c->pptr[r] = (int32_t)path_ptr[r];
+  c->plinks.assign(path_links, path_links + c->nnz);
+  c->dptr.assign(demand_path_ptr, demand_path_ptr + n_demands + 1);
+  // link -> path CSC, paths ascending within a link
+  c->lptr.assign(n_links + 1, 0);
+  for (int32_t i = 0; i < c->nnz; ++i) c->lptr[c->plinks[i] + 1]++;
+  for (int32_t e = 0; e < n_links; ++e) c->lptr[e + 1] += c->lptr[e];
+  c->lpaths.resize(c->nnz);
+  {
+    std::vector<int32_t> fill(c->lptr.begin(), c->lptr.end() - 1);
+    for (int32_t r = 0; r < n_paths; ++r)
+      for (int32_t i = c->pptr[r]; i < c->pptr[r + 1]; ++i) c->lpaths[fill[c->plinks[i]]++] = r;
+  }
+  c->maxp = 0;
+  for (int32_t k = 0; k < n_demands; ++k) c->maxp = std::max(c->maxp, c->dptr[k + 1] - c->dptr[k]);
+  c->G = 1;
+  c->logG = 0;
+  while (c->G < c->maxp) {
+    c->G <<= 1;
+    c->logG++;
+  }
+  normalise(c);
+  c->lds_bytes = block_lds_bytes(c->E, c->P, c->D, c->nnz);
+
+  auto cleanup_fail = [&](te_status s) {
+    te_destroy(c);
+    return s;
+  };
+  if (hipSetDevice(hip_device) != hipSuccess) return cleanup_fail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
+  // index pool: pptr | plinks | dptr | lptr | lpaths
+  const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz;
+  const int nA = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
+  bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
+            dalloc(&c->d_Cn, c->E) == hipSuccess && dalloc(&c->st.x, c->P) == hipSuccess &&
+            dalloc(&c->st.uneg, c->P) == hipSuccess && dalloc(&c->st.udem, c->D) == hipSuccess &&
+            dalloc(&c->st.S, c->D) == hipSuccess && dalloc(&c->st.gq, c->E) == hipSuccess &&
+            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA * 4) == hipSuccess &&
+            dalloc(&c->st.partB, (size_t)2 * kLinkBlocks * 4) == hipSuccess &&
+            dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
+            dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
+            dalloc(&c->pb.lsc, c->P) == hipSuccess && dalloc(&c->pb.trim, c->P) == hipSuccess &&
+            dalloc(&c->d_params, 1) == hipSuccess && dalloc(&c->d_desc, 1) == hipSuccess &&
+            dalloc(&c->d_bout, 1) == hipSuccess;
+  if (!ok) return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
+  if (hipHostMalloc((void **)&c->h_params, sizeof(Params)) != hipSuccess ||
+      hipHostMalloc((void **)&c->h_flag, sizeof(int32_t) * 4) != hipSuccess)
+    return cleanup_fail(fail(TE_ERR_OOM, "pinned host allocation failed"));
+  if (hipEventCreate(&c->params_ev) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+      hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->pe[0]) != hipSuccess ||
+      hipEventCreate(&c->pe[1]) != hipSuccess)
+    return cleanup_fail(fail(TE_ERR_DEVICE, "event creation failed"));
+  c->st.nA = nA;
+  c->st.nB = kLinkBlocks;
+  {
+    std::vector<int32_t> pool;
+    pool.reserve(ni);
+    pool.insert(pool.end(), c->pptr.begin(), c->pptr.end());
+    pool.insert(pool.end(), c->plinks.begin(), c->plinks.end());
+    pool.insert(pool.end(), c->dptr.begin(), c->dptr.end());
+    pool.insert(pool.end(), c->lptr.begin(), c->lptr.end());
+    pool.insert(pool.end(), c->lpaths.begin(), c->lpaths.end());
+    if (hipMemcpy(c->d_i32, pool.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the index pool failed"));
+  }
+  te_status s = upload_values(c);
+  if (s != TE_OK) return cleanup_fail(s);
+  Prob &p = c->prob;
+  p.E = c->E;
+  p.P = c->P;
+  p.D = c->D;
+  p.nnz = c->nnz;
+  p.G = c->G;
+  p.logG = c->logG;
+  p.pptr = c->d_i32;
+  p.plinks = p.pptr + c->P + 1;
+  p.dptr = p.plinks + c->nnz;
+  p.lptr = p.dptr + c->D + 1;
+  p.lpaths = p.lptr + c->E + 1;
+  p.Dn = c->d_Dn;
+  p.Cn = c->d_Cn;
+  *out = c;
+  return TE_OK;
+}
+
+te_status te_update(te_ctx *c, const double *capacity, const double *demand) {
+  if (!c) return fail(TE_ERR_INVALID, "null handle");
+  std::vector<double> cap = capacity ? std::vector<double>(capacity, capacity + c->E) : c->cap;
+  std::vector<double> dem = demand ? std::vector<double>(demand, demand + c->D) : c->dem;
+  std::vector<int64_t> pp(c->pptr.begin(), c->pptr.end());
+  te_status v = te_validate(c->E, cap.data(), c->P, pp.data(), c->plinks.data(), c->D, c->dptr.data(), dem.data());
+  if (v != TE_OK) return v;
+  c->cap = cap;
+  c->dem = dem;
+  normalise(c);
+  return upload_values(c);
+}
+
+te_status te_info(const te_ctx *c, int64_t *sz) {
+  if (!c || !sz) return fail(TE_ERR_INVALID, "null argument");
+  sz[0] = c->E;
+  sz[1] = c->P;
+  sz[2] = c->D;
+  sz[3] = c->nnz;
+  sz[4] = c->maxp;
+  sz[5] = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
+  return TE_OK;
+}
+
+te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const float *x0_dev, float *x_out_dev,
+                   float *S_out_dev, te_stats *stats) {
+  if (!c || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or output");
+  te_options o;
+  if (opt) o = *opt; else te_default_options(&o);
+  te_status s = check_options(&o);
+  if (s != TE_OK) return s;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(c->device));
+  int engine = o.engine;
+  if (engine == TE_ENGINE_AUTO) engine = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
+  if (engine == TE_ENGINE_BLOCK && c->lds_bytes > kMaxBlockLds)
+    return fail(TE_ERR_INVALID, "instance needs %zu bytes of LDS, more than one workgroup has", c->lds_bytes);
+  s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
+  if (s != TE_OK) return s;
+  HIPCHK(hipEventRecord(c->ev0, stream));
+  if (engine == TE_ENGINE_BLOCK) {
+    Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev};
+    HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
+                              c->lds_bytes, stream));
+  } else {
+    s = build_chunk_graph(c, stream);
+    if (s != TE_OK) return s;
+    HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, (float)(1.0 / c->scale), stream));
+    int launched = 0;
+    if (o.fixed_iters > 0) {
+      const int K = o.fixed_iters;
+      while (launched + kChunk <= K) {
+        HIPCHK(hipGraphLaunch(c->chunk, stream));
+        launched += kChunk;
+      }
+      while (launched < K) {
+        HIPCHK(launch_iteration(c->prob, c->st, c->d_params, launched & 1, stream));
+        ++launched;
+      }
+    } else {
+      // adaptive: chunks until the device-side stop flag is seen (one chunk in flight ahead)
+      const int K = o.max_iters;
+      bool stopped = false;
+      while (launched < K && !stopped) {
+        HIPCHK(hipGraphLaunch(c->chunk, stream));
+        launched += kChunk;
+        const int slot = (launched / kChunk) & 1;
+        HIPCHK(hipMemcpyAsync(&c->h_flag[slot], &c->st.ctrl[(launched - 1) & 1].stop, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipEventRecord(c->pe[slot], stream));
+        if (launched / kChunk >= 2) {
+          const int prev = slot ^ 1;
+          HIPCHK(hipEventSynchronize(c->pe[prev]));
+          if (c->h_flag[prev]) stopped = true;
+        }
+      }
+    }
+    const int last_par = launched > 0 ? (launched - 1) & 1 : 1;
+    HIPCHK(launch_finish(c->st, c->d_params, last_par, stream));
+    HIPCHK(launch_project(c->prob, c->st, c->pb, x_out_dev, S_out_dev, c->scale, o.project, stream));
+  }
+  HIPCHK(hipEventRecord(c->ev1, stream));
+  if (stats) {
+    HIPCHK(hipStreamSynchronize(stream));
+    Ctrl fin{};
+    if (engine == TE_ENGINE_BLOCK) {
+      BatchOut bo;
+      HIPCHK(hipMemcpy(&bo, c->d_bout, sizeof(bo), hipMemcpyDeviceToHost));
+      fin.k = bo.iters;
+      fin.flags = bo.flags;
+      fin.stop_iter = bo.stop_iter;
+      fin.alpha = bo.alpha;
+      fin.beta = bo.beta;
+      fin.r = bo.r;
+      fin.s = bo.s;
+      fin.cap_viol = bo.cap_viol;
+      fin.dem_viol = bo.dem_viol;
+    } else {
+      HIPCHK(hipMemcpy(&fin, c->st.ctrl + 2, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    }
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    fill_stats(stats, fin, engine, ms);
+    if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
+      return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
+  }
+  return TE_OK;
+}
+
+te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_dev, double *dD_dev) {
+  (void)hip_stream;
+  (void)dS_dev;
+  (void)dC_dev;
+  (void)dD_dev;
+  if (!c) return fail(TE_ERR_INVALID, "null handle");
+  return fail(TE_ERR_STATE, "no recorded solve on this handle");
+}
+
+void te_destroy(te_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
+  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.x, c->st.uneg, c->st.udem, c->st.S, c->st.gq, c->st.ctrl,
+                  c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
+                  c->d_params, c->d_desc, c->d_bout, c->d_sched};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->h_params) (void)hipHostFree(c->h_params);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->params_ev) (void)hipEventDestroy(c->params_ev);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->pe)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
+
+// ----------------------------------------------------------------------------------------------
+// batches
+// ----------------------------------------------------------------------------------------------
+te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
+  if (!out || !inst || n <= 0) return fail(TE_ERR_INVALID, "invalid batch arguments");
+  *out = nullptr;
+  const int dev = inst[0]->device;
+  te_batch *b = new (std::nothrow) te_batch();
+  if (!b) return fail(TE_ERR_OOM, "host allocation");
+  b->device = dev;
+  b->n = n;
+  std::vector<int32_t> pool;
+  std::vector<float> Dn;
+  std::vector<double> Cn;
+  int64_t offE = 0, offP = 0, offD = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    const te_ctx *c = inst[k];
+    if (!c || c->device != dev) {
+      delete b;
+      return fail(TE_ERR_INVALID, "batch instance %d is null or on another device", k);
+    }
+    if (c->lds_bytes > kMaxBlockLds) {
+      delete b;
+      return fail(TE_ERR_INVALID, "batch instance %d needs %zu bytes of LDS", k, c->lds_bytes);
+    }
+    BatchDesc d{};
+    d.E = c->E;
+    d.P = c->P;
+    d.D = c->D;
+    d.nnz = c->nnz;
+    d.G = c->G;
+    d.logG = c->logG;
+    d.off_pptr = (int64_t)pool.size();
+    pool.insert(pool.end(), c->pptr.begin(), c->pptr.end());
+    d.off_plinks = (int64_t)pool.size();
+    pool.insert(pool.end(), c->plinks.begin(), c->plinks.end());
+    d.off_dptr = (int64_t)pool.size();
+    pool.insert(pool.end(), c->dptr.begin(), c->dptr.end());
+    d.off_lptr = (int64_t)pool.size();
+    pool.insert(pool.end(), c->lptr.begin(), c->lptr.end());
+    d.off_lpaths = (int64_t)pool.size();
+    pool.insert(pool.end(), c->lpaths.begin(), c->lpaths.end());
+    d.off_E = offE;
+    d.off_P = offP;
+    d.off_D = offD;
+    d.scale = c->scale;
+    Dn.insert(Dn.end(), c->Dn.begin(), c->Dn.end());
+    Cn.insert(Cn.end(), c->Cn.begin(), c->Cn.end());
+    offE += c->E;
+    offP += c->P;
+    offD += c->D;
+    b->lds_bytes = std::max(b->lds_bytes, c->lds_bytes);
+    b->desc.push_back(d);
+  }
+  b->totP = offP;
+  b->totD = offD;
+  auto bail = [&](te_status s) {
+    te_destroy_batch(b);
+    return s;
+  };
+  if (hipSetDevice(dev) != hipSuccess) return bail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
+  bool ok = dalloc(&b->d_desc, n) == hipSuccess && dalloc(&b->d_out, n) == hipSuccess &&
+            dalloc(&b->d_i32, pool.size()) == hipSuccess && dalloc(&b->d_Dn, Dn.size()) == hipSuccess &&
+            dalloc(&b->d_Cn, Cn.size()) == hipSuccess && dalloc(&b->d_params, 1) == hipSuccess;
+  if (!ok) return bail(fail(TE_ERR_OOM, "device allocation failed"));
+  if (hipHostMalloc((void **)&b->h_params, sizeof(Params)) != hipSuccess)
+    return bail(fail(TE_ERR_OOM, "pinned host allocation failed"));
+  if (hipEventCreate(&b->params_ev) != hipSuccess || hipEventCreate(&b->ev0) != hipSuccess ||
+      hipEventCreate(&b->ev1) != hipSuccess)
+    return bail(fail(TE_ERR_DEVICE, "event creation failed"));
+  if (hipMemcpy(b->d_desc, b->desc.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_i32, pool.data(), sizeof(int32_t) * pool.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_Dn, Dn.data(), sizeof(float) * Dn.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_Cn, Cn.data(), sizeof(double) * Cn.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return bail(fail(TE_ERR_DEVICE, "batch upload failed"));
+  *out = b;
+  return TE_OK;
+}
+
+te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, float *x_out_dev, float *S_out_dev,
+                         te_stats *stats) {
+  if (!b || !x_out_dev) return fail(TE_ERR_INVALID, "null batch or output");
+  te_options o;
+  if (opt) o = *opt; else te_default_options(&o);
+  te_status s = check_options(&o);
+  if (s != TE_OK) return s;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(b->device));
+  s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &o, stream);
+  if (s != TE_OK) return s;
+  HIPCHK(hipEventRecord(b->ev0, stream));
+  Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
+  HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, o.project, x_out_dev, S_out_dev, b->d_out,
+                            b->lds_bytes, stream));
+  HIPCHK(hipEventRecord(b->ev1, stream));
+  if (stats) {
+    HIPCHK(hipStreamSynchronize(stream));
+    std::vector<BatchOut> outs(b->n);
+    HIPCHK(hipMemcpy(outs.data(), b->d_out, sizeof(BatchOut) * b->n, hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    for (int32_t k = 0; k < b->n; ++k) {
+      Ctrl fin{};
+      fin.k = outs[k].iters;
+      fin.flags = outs[k].flags;
+      fin.stop_iter = outs[k].stop_iter;
+      fin.alpha = outs[k].alpha;
+      fin.beta = outs[k].beta;
+      fin.r = outs[k].r;
+      fin.s = outs[k].s;
+      fin.cap_viol = outs[k].cap_viol;
+      fin.dem_viol = outs[k].dem_viol;
+      fill_stats(&stats[k], fin, TE_ENGINE_BLOCK, ms);
+    }
+  }
+  return TE_OK;
+}
+
+void te_destroy_batch(te_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  void *bufs[] = {b->d_desc, b->d_out, b->d_i32, b->d_Dn, b->d_Cn, b->d_params, b->d_sched};
+  for (void *p : bufs)
+    if (p) (void)hipFree(p);
+  if (b->h_params) (void)hipHostFree(b->h_params);
+  if (b->params_ev) (void)hipEventDestroy(b->params_ev);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+  delete b;
+}
+
+}  // extern "C"
