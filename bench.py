@@ -1,0 +1,227 @@
+"""Benchmark of the GATE TE solve on one MI355X.
+
+Metric: milliseconds to reach a solve within 1% of the max-min optimum (the paper's optimality
+metric, section 4.1, >= 0.99 after the projection of Algorithm 2), and scenarios/s of the batched
+solve against plain single-instance solves.
+
+Workload (one "step" = one complete solve: initialisation, K* iterations of Algorithm 1 and the
+projection, inputs resident in device memory): the 150-node instance -- seeded Waxman graph with
+~600 bidirectional links (capacities {100, 400}), all 22,350 ordered pairs with gravity demands
+(lognormal(0, 1.5) node weights) at 1.3x the path-restricted max concurrent flow, 8
+latency-shortest paths per pair.  K* is the smallest iteration budget on a geometric grid whose
+projected allocation reaches optimality >= 0.99 against the exact max-min allocation (progressive
+filling LPs, stored in tests/golden).
+
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batch]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ms to reach 1%-of-optimal max-min TE solve; scenarios/sec batched vs plain"
+HBM_PEAK_GBS = 8000.0
+THETA = 1e-9  # optimality floor in normalised units (below every synthetic demand)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(inst):
+    """Algorithmic bytes per launch of the two per-iteration kernels (int32 indices, FP32 path state,
+    FP64 per-link / per-demand duals).  Each kernel is charged what it must read or write once:
+      demand kernel: path row pointers 4 (P+1), link ids 4 nnz, x and u_neg read+write 16 P,
+                     per-link (g, q) pairs 16 E, per demand ptr+D 8 + u_dem/S read+write 32 -> 40 D
+      link kernel:   CSC path ids 4 nnz, x read 4 P, (g, q) read+write 32 E, capacity 8 E,
+                     non-empty link tables 8 E."""
+    P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
+    b_dem = 4 * (P + 1) + 4 * nnz + 16 * P + 16 * E + 40 * D
+    b_link = 4 * nnz + 4 * P + 48 * E
+    return b_dem, b_link
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--n-scen", type=int, default=512)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              f"sharding is a design note, not an implemented path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle as O
+    import paper_2605_01748_amd as te
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    te.library()
+    dev = torch.device("cuda", 0)
+
+    t0 = time.time()
+    inst = W.config2(0)
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_config2_s0.npz"))
+    assert str(gold["fingerprint"]) == inst.fingerprint(), "instance does not match the stored max-min allocation"
+    opt_S = gold["S"]
+    log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
+    prob = te.Problem(inst)
+    scale = float(inst.capacity[np.unique(inst.path_links)].max())
+
+    def run(K, project=True, **kw):
+        x, S, st = prob.solve(te.Options(fixed_iters=K, project=project, engine=te.ENGINE_GRAPH, **kw))
+        return x, S, st
+
+    def optimality(S):
+        return O.optimality(S.cpu().numpy().astype(np.float64), opt_S, THETA * scale)
+
+    # ---- K*: smallest budget on a geometric grid (ratio 2^(1/4)) reaching >= 0.99 ----
+    grid = sorted({int(round(32 * 2 ** (i / 4))) for i in range(0, 44)})
+    K_star, opt_at = None, None
+    for K in grid:
+        _, S, st = run(K)
+        o = optimality(S)
+        log(f"  K={K:6d} optimality {o:.5f} alpha {st['final_alpha']:.0f} beta {st['beta']:.4g}")
+        if o >= 0.99:
+            K_star, opt_at = K, o
+            break
+    if K_star is None:
+        raise SystemExit("no iteration budget on the grid reached 0.99 optimality")
+
+    # ---- timed region: whole solves at K* ----
+    for _ in range(args.warmup):
+        run(K_star)
+    torch.cuda.synchronize()
+    times = []
+    stream = torch.cuda.current_stream(dev)
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        prob.solve(te.Options(fixed_iters=K_star, engine=te.ENGINE_GRAPH), stats=False)
+        e1.record(stream)
+        times.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ev_ms = [a.elapsed_time(b) for a, b in times]
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"K*={K_star}: {ms_per_step:.3f} ms per solve (wall), median event {np.median(ev_ms):.3f} ms")
+
+    # ---- per-kernel device time (HIP events around each launch) and roofline ----
+    ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=min(K_star, 1024))
+    b_dem, b_link = kernel_bytes(inst)
+    dom = ("k_demand", ms_dem, b_dem) if ms_dem * 1 >= ms_link else ("k_link", ms_link, b_link)
+    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom[0],
+                "bytes_per_launch": int(dom[2]), "avg_launch_us": round(dom[1] * 1e3, 3),
+                "other_kernel": {"k_demand_us": round(ms_dem * 1e3, 3), "k_link_us": round(ms_link * 1e3, 3),
+                                 "k_demand_bytes": int(b_dem), "k_link_bytes": int(b_link)}}
+    log(f"kernels: demand {ms_dem * 1e3:.2f} us, link {ms_link * 1e3:.2f} us")
+
+    # ---- error against the FP64 oracle at the same K* (oracle's schedule replayed) ----
+    orc_S = None
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = os.cpu_count() or 1
+        os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+        t1 = time.perf_counter()
+        r = O.solve(inst, O.Options(fixed_iters=K_star), want_state=False)
+        t_orc = time.perf_counter() - t1
+        orc_S = r.S_raw * r.scale
+        sb, sa = r.schedule
+        _, S_rep, _ = run(K_star, project=False, sched_beta=sb, sched_alpha=sa)
+        S_rep = S_rep.cpu().numpy().astype(np.float64)
+        floor = 1e-2 * inst.demand.max()
+        err = np.abs(S_rep - orc_S) / np.maximum(np.abs(orc_S), floor)
+        cpu = {"value": round(t_orc * 1e3, 1), "unit": "ms", "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
+               "kind": "oracle",
+               "sample": f"one full FP64 oracle solve of the same instance at K*={K_star} iterations "
+                         f"(OpenMP, {os.environ.get('OMP_NUM_THREADS')} threads), same unit as value",
+               "oracle_optimality": round(O.optimality(r.S, opt_S, THETA * scale), 5),
+               "gpu_vs_oracle_max_rel_err": float(f"{err.max():.3e}")}
+        log(f"oracle: {t_orc * 1e3:.1f} ms, GPU-vs-oracle max rel err {err.max():.3e}")
+
+    # ---- batched scenarios vs plain solves (the second half of the metric) ----
+    batch = None
+    if not args.no_batch:
+        t2 = time.time()
+        c1 = W.config1(0)
+        g1 = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_config1_s0.npz"))["S"]
+        p1 = te.Problem(c1)
+        K1 = None
+        for K in grid:
+            _, S, _ = p1.solve(te.Options(fixed_iters=K, engine=te.ENGINE_BLOCK))
+            if O.optimality(S.cpu().numpy().astype(np.float64), g1, THETA * 100.0) >= 0.99:
+                K1 = K
+                break
+        scen = W.config4_scenarios(0, n_scen=args.n_scen)
+        probs = [te.Problem(s) for s in scen]
+        bt = te.Batch(probs)
+        o1 = te.Options(fixed_iters=K1)
+        bt.solve(o1, stats=False)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            bt.solve(o1, stats=False)
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - tb) / reps
+        n_plain = min(64, len(probs))
+        for p in probs[:2]:
+            p.solve(te.Options(fixed_iters=K1), stats=False)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for p in probs[:n_plain]:
+            p.solve(te.Options(fixed_iters=K1), stats=False)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - tp) / n_plain
+        batch = {"scenarios": len(probs), "K": K1, "batched_scenarios_per_s": round(len(probs) / t_batch, 1),
+                 "plain_scenarios_per_s": round(1.0 / t_plain, 1),
+                 "speedup": round((len(probs) / t_batch) * t_plain, 2),
+                 "workload": "config-1 topology, 1-3 link cuts, lognormal(0,0.3) demand noise, k_c in 2..8"}
+        log(f"batch: {batch} ({time.time() - t2:.1f}s)")
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "config2: 150-node Waxman, ~600 links, 22350 gravity demands (lognormal 1.5), "
+                               "1.3x max concurrent flow, k=8 latency-shortest paths, max-min target",
+                   "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
+                   "K_star": K_star, "optimality": round(opt_at, 5), "engine": "graph",
+                   "median_event_ms": round(float(np.median(ev_ms)), 4)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "batched": batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

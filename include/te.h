@@ -181,6 +181,15 @@ te_status te_create_batch(int32_t n, te_ctx *const *instances, te_batch **out);
 te_status te_solve_batch(te_batch *batch, const te_options *opt, void *hip_stream, float *x_out_dev,
                          float *S_out_dev, te_stats *stats);
 
+/*
+ * Device time of the graph engine's two per-iteration kernels (profiling aid): runs the solve of
+ * opt with opt->fixed_iters = iters as individually launched kernels on hip_stream with a HIP event
+ * before and after every launch, synchronises, and writes the mean duration in milliseconds of the
+ * demand kernel to ms_out[0] and of the link kernel to ms_out[1].  The work is that of te_solve
+ * without the projection.  iters in 1..4096.
+ */
+te_status te_kernel_times(te_ctx *ctx, const te_options *opt, void *hip_stream, int32_t iters, double *ms_out);
+
 void te_destroy(te_ctx *ctx);
 void te_destroy_batch(te_batch *batch);
 

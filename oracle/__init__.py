@@ -8,6 +8,7 @@ code with the HIP library.
                     ``libgate_oracle.so`` built from ``gate_oracle.c``.
 * ``sum_root``   -- one commodity's sum equation (appendix B.2).
 * ``project``    -- Algorithm 2 (section 3.5).
+* ``grad``       -- FP64 reverse pass (vector-Jacobian product) through K sweeps.
 * ``maxmin``     -- exact max-min fair allocation by progressive filling of LPs
                     (``maxmin.py``).
 * ``optimality`` -- the paper's optimality metric (section 4.1).
@@ -77,6 +78,9 @@ def _load():
         lib.gate_oracle_sum_root.restype = ctypes.c_int
         lib.gate_oracle_sum_root.argtypes = [ctypes.c_int, P, P, P, ctypes.c_double, ctypes.c_double,
                                              ctypes.c_double, ctypes.c_double, ctypes.c_double, P, P]
+        lib.gate_oracle_grad.restype = ctypes.c_int
+        lib.gate_oracle_grad.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P, P, ctypes.c_double,
+                                         ctypes.c_int, P, P, P, P, P, P]
         lib.gate_oracle_project.restype = ctypes.c_int
         lib.gate_oracle_project.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P, P,
                                             ctypes.c_double, P]
@@ -232,6 +236,37 @@ def project(inst, x, alpha):
     lib.gate_oracle_project(inst.n_links, cap.ctypes.data, inst.n_paths, pptr.ctypes.data, plinks.ctypes.data,
                             inst.n_demands, dptr.ctypes.data, dem.ctypes.data, float(alpha), xx.ctypes.data)
     return xx
+
+
+def used_scale(inst):
+    """The unit scale s: the largest capacity of a link used by some path."""
+    return float(inst.capacity[np.unique(inst.path_links)].max())
+
+
+def grad(inst, sched_beta, sched_alpha, dS, scale=None, capacity=None, demand=None):
+    """FP64 reverse pass: S^(K) (unprojected, caller units) and the vector-Jacobian products
+    dC = dS . dS^(K)/dC, dD = dS . dS^(K)/dD for K = len(sched_beta) sweeps with the schedule and
+    the unit scale held fixed.  capacity / demand override the instance's values (for finite
+    differences at a frozen scale)."""
+    lib = _load()
+    sb = np.ascontiguousarray(sched_beta, np.float64)
+    sa = np.ascontiguousarray(sched_alpha, np.float64)
+    cap = np.ascontiguousarray(inst.capacity if capacity is None else capacity, np.float64)
+    dem = np.ascontiguousarray(inst.demand if demand is None else demand, np.float64)
+    pptr = np.ascontiguousarray(inst.path_ptr, np.int64)
+    plinks = np.ascontiguousarray(inst.path_links, np.int32)
+    dptr = np.ascontiguousarray(inst.demand_path_ptr, np.int32)
+    w = np.ascontiguousarray(dS, np.float64)
+    S = np.zeros(inst.n_demands)
+    dC = np.zeros(inst.n_links)
+    dD = np.zeros(inst.n_demands)
+    s = used_scale(inst) if scale is None else float(scale)
+    rc = lib.gate_oracle_grad(inst.n_links, cap.ctypes.data, inst.n_paths, pptr.ctypes.data, plinks.ctypes.data,
+                              inst.n_demands, dptr.ctypes.data, dem.ctypes.data, s, sb.shape[0], sb.ctypes.data,
+                              sa.ctypes.data, w.ctypes.data, S.ctypes.data, dC.ctypes.data, dD.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("oracle grad failed")
+    return S, dC, dD
 
 
 def demand_sums(inst, x):

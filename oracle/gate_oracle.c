@@ -670,3 +670,288 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   free(gq_g); free(gq_q); free(dr); free(ds); free(dd); free(de); free(steps_c);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Reverse pass (vector-Jacobian product) through K sweeps                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Differentiates the unprojected sums S^(K)_c = sum_{r in P_c} x^(K)_r with respect to the
+ * capacities C_e and demands D_c, for K sweeps of the full per-incidence iteration above with
+ * the (beta_k, alpha_k) schedule given and the unit scale s given (both held fixed).  Every
+ * [.]_+ takes its derivative on the branch taken (1 if the argument is > 0, else 0); the root
+ * S*_c of the sum equation is differentiated through the implicit function theorem,
+ * dS* = -(dF/dtheta) / (dF/dS).  The forward states of all K sweeps are kept in memory.
+ *
+ * Inputs in caller units; dS [D] cotangent on S^(K) (caller units); outputs dC [E], dD [D] are
+ * gradients in caller units (with s fixed they equal the normalised-unit gradients).
+ */
+typedef struct {
+  double *y, *ucon, *ucap, *udem, *uneg; /* state at the start of the sweep */
+  double *x;                              /* x^{k+1} after the x-block */
+  double *Sst;                            /* roots S*_c */
+  double *S;                              /* sums of x^{k+1} */
+  double *g;                              /* per-link g of the y-block */
+  double *W;                              /* per-link W of the y-block */
+  double *yn;                             /* y^{k+1} */
+} sweep_t;
+
+int gate_oracle_grad(int n_links, const double *capacity, int n_paths, const int64_t *path_ptr,
+                     const int32_t *path_links, int n_demands, const int32_t *demand_path_ptr,
+                     const double *demand, double scale, int K, const double *sched_beta,
+                     const double *sched_alpha, const double *dS, double *S_out, double *dC, double *dD) {
+  const int E = n_links, P = n_paths, D = n_demands;
+  const int64_t nnz = path_ptr[P];
+  if (!(scale > 0.0) || K <= 0) return 1;
+  double *C = (double *)malloc(sizeof(double) * (size_t)E);
+  double *Dm = (double *)malloc(sizeof(double) * (size_t)D);
+  for (int e = 0; e < E; ++e) C[e] = capacity[e] / scale;
+  for (int c = 0; c < D; ++c) Dm[c] = demand[c] / scale;
+  int *n_r = (int *)malloc(sizeof(int) * (size_t)P);
+  int *dem_of = (int *)malloc(sizeof(int) * (size_t)P);
+  for (int r = 0; r < P; ++r) n_r[r] = (int)(path_ptr[r + 1] - path_ptr[r]);
+  for (int c = 0; c < D; ++c) for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r) dem_of[r] = c;
+  int32_t *lptr = (int32_t *)calloc((size_t)E + 1, sizeof(int32_t));
+  for (int64_t i = 0; i < nnz; ++i) lptr[path_links[i] + 1]++;
+  for (int e = 0; e < E; ++e) lptr[e + 1] += lptr[e];
+  int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)E);
+  memcpy(fill, lptr, sizeof(int32_t) * (size_t)E);
+  int64_t *linc = (int64_t *)malloc(sizeof(int64_t) * (size_t)nnz);
+  int32_t *inc_path = (int32_t *)malloc(sizeof(int32_t) * (size_t)nnz);
+  for (int r = 0; r < P; ++r)
+    for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) {
+      linc[fill[path_links[i]]++] = i;
+      inc_path[i] = r;
+    }
+
+  sweep_t *sw = (sweep_t *)calloc((size_t)K, sizeof(sweep_t));
+  double *y = (double *)malloc(sizeof(double) * (size_t)nnz);
+  double *ucon = (double *)calloc((size_t)nnz, sizeof(double));
+  double *ucap = (double *)calloc((size_t)E, sizeof(double));
+  double *udem = (double *)calloc((size_t)D, sizeof(double));
+  double *uneg = (double *)calloc((size_t)P, sizeof(double));
+  double *Sws = (double *)malloc(sizeof(double) * (size_t)D);
+  double *a = (double *)malloc(sizeof(double) * (size_t)P);
+  for (int c = 0; c < D; ++c) {
+    int m = demand_path_ptr[c + 1] - demand_path_ptr[c];
+    for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r)
+      for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) y[i] = Dm[c] / m;
+    Sws[c] = Dm[c];
+  }
+#define ALLOC(n) (double *)malloc(sizeof(double) * (size_t)((n) ? (n) : 1))
+  /* forward */
+  for (int k = 0; k < K; ++k) {
+    sweep_t *s = &sw[k];
+    const double alpha = sched_alpha[k], beta = sched_beta[k];
+    s->y = ALLOC(nnz); memcpy(s->y, y, sizeof(double) * (size_t)nnz);
+    s->ucon = ALLOC(nnz); memcpy(s->ucon, ucon, sizeof(double) * (size_t)nnz);
+    s->ucap = ALLOC(E); memcpy(s->ucap, ucap, sizeof(double) * (size_t)E);
+    s->udem = ALLOC(D); memcpy(s->udem, udem, sizeof(double) * (size_t)D);
+    s->uneg = ALLOC(P); memcpy(s->uneg, uneg, sizeof(double) * (size_t)P);
+    s->x = ALLOC(P); s->Sst = ALLOC(D); s->S = ALLOC(D); s->g = ALLOC(E); s->W = ALLOC(E); s->yn = ALLOC(nnz);
+    for (int c = 0; c < D; ++c) {
+      int r0 = demand_path_ptr[c], m = demand_path_ptr[c + 1] - r0;
+      for (int r = r0; r < r0 + m; ++r) {
+        double acc = 0.0;
+        for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) acc += y[i] - ucon[i];
+        a[r] = acc;
+      }
+      commodity_t cm = {m, a + r0, n_r + r0, uneg + r0, Dm[c], udem[c], alpha, beta};
+      int steps;
+      double Sst = sum_root(&cm, Sws[c], 200, &steps);
+      double h = h_of(&cm, Sst), sum = 0.0;
+      for (int r = r0; r < r0 + m; ++r) { s->x[r] = xi(a[r] - h, n_r[r], uneg[r]); sum += s->x[r]; }
+      s->Sst[c] = Sst;
+      s->S[c] = sum;
+      Sws[c] = Sst;
+    }
+    for (int e = 0; e < E; ++e) {
+      int ne = lptr[e + 1] - lptr[e];
+      double V = 0.0;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) V += s->x[inc_path[linc[j]]] + ucon[linc[j]];
+      double W = ucap[e] + V - C[e];
+      double g = (W > 0.0 ? W : 0.0) / (1 + ne);
+      s->W[e] = W;
+      s->g[e] = g;
+      double ysum = 0.0;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) {
+        int64_t i = linc[j];
+        s->yn[i] = s->x[inc_path[i]] + ucon[i] - g;
+        ysum += s->yn[i];
+      }
+      double uc = ucap[e] + ysum - C[e];
+      ucap[e] = uc > 0.0 ? uc : 0.0;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) {
+        int64_t i = linc[j];
+        double u = ucon[i] + s->x[inc_path[i]] - s->yn[i];
+        ucon[i] = u > 0.0 ? u : 0.0;
+      }
+    }
+    memcpy(y, s->yn, sizeof(double) * (size_t)nnz);
+    for (int c = 0; c < D; ++c) { double u = udem[c] + s->S[c] - Dm[c]; udem[c] = u > 0.0 ? u : 0.0; }
+    for (int r = 0; r < P; ++r) { double u = uneg[r] - s->x[r]; uneg[r] = u > 0.0 ? u : 0.0; }
+    double f = (k + 1 < K) ? sched_beta[k + 1] / sched_beta[k] : 1.0;
+    if (f != 1.0) {
+      for (int c = 0; c < D; ++c) udem[c] /= f;
+      for (int e = 0; e < E; ++e) ucap[e] /= f;
+      for (int r = 0; r < P; ++r) uneg[r] /= f;
+      for (int64_t i = 0; i < nnz; ++i) ucon[i] /= f;
+    }
+  }
+  if (S_out) for (int c = 0; c < D; ++c) S_out[c] = sw[K - 1].S[c] * scale;
+
+  /* reverse: adjoints of the state after sweep k (before the rescale of that sweep) */
+  double *bx = (double *)calloc((size_t)P, sizeof(double));      /* x^{k+1} */
+  double *by = (double *)calloc((size_t)nnz, sizeof(double));    /* y^{k+1} */
+  double *bucon = (double *)calloc((size_t)nnz, sizeof(double));
+  double *bucap = (double *)calloc((size_t)E, sizeof(double));
+  double *budem = (double *)calloc((size_t)D, sizeof(double));
+  double *buneg = (double *)calloc((size_t)P, sizeof(double));
+  double *bC = (double *)calloc((size_t)E, sizeof(double));
+  double *bD = (double *)calloc((size_t)D, sizeof(double));
+  double *nby = (double *)calloc((size_t)nnz, sizeof(double));  /* adjoint of y^k (input) */
+  double *nucon = (double *)calloc((size_t)nnz, sizeof(double));
+  double *nucap = (double *)calloc((size_t)E, sizeof(double));
+  double *nudem = (double *)calloc((size_t)D, sizeof(double));
+  double *nuneg = (double *)calloc((size_t)P, sizeof(double));
+  double *bS = (double *)calloc((size_t)D, sizeof(double));
+  double *ba = (double *)calloc((size_t)P, sizeof(double));
+  /* S^(K) = sum x^(K): seed */
+  for (int c = 0; c < D; ++c)
+    for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r) bx[r] = dS[c];
+  for (int k = K - 1; k >= 0; --k) {
+    sweep_t *s = &sw[k];
+    const double alpha = sched_alpha[k], beta = sched_beta[k];
+    const double f = (k + 1 < K) ? sched_beta[k + 1] / sched_beta[k] : 1.0;
+    /* rescale of sweep k: u_out = u_pre / f */
+    for (int c = 0; c < D; ++c) budem[c] /= f;
+    for (int e = 0; e < E; ++e) bucap[e] /= f;
+    for (int r = 0; r < P; ++r) buneg[r] /= f;
+    for (int64_t i = 0; i < nnz; ++i) bucon[i] /= f;
+    memset(nby, 0, sizeof(double) * (size_t)nnz);
+    memset(nucon, 0, sizeof(double) * (size_t)nnz);
+    memset(nucap, 0, sizeof(double) * (size_t)E);
+    memset(nudem, 0, sizeof(double) * (size_t)D);
+    memset(nuneg, 0, sizeof(double) * (size_t)P);
+    memset(bS, 0, sizeof(double) * (size_t)D);
+    /* dual updates */
+    for (int r = 0; r < P; ++r) {
+      double m = (s->uneg[r] - s->x[r] > 0.0) ? 1.0 : 0.0;
+      nuneg[r] += m * buneg[r];
+      bx[r] -= m * buneg[r];
+    }
+    for (int c = 0; c < D; ++c) {
+      double m = (s->udem[c] + s->S[c] - Dm[c] > 0.0) ? 1.0 : 0.0;
+      nudem[c] += m * budem[c];
+      bS[c] += m * budem[c];
+      bD[c] -= m * budem[c];
+    }
+    for (int e = 0; e < E; ++e) {
+      double ysum = 0.0;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) ysum += s->yn[linc[j]];
+      double m = (s->ucap[e] + ysum - C[e] > 0.0) ? 1.0 : 0.0;
+      nucap[e] += m * bucap[e];
+      bC[e] -= m * bucap[e];
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) {
+        int64_t i = linc[j];
+        by[i] += m * bucap[e];
+        double mi = (s->ucon[i] + s->x[inc_path[i]] - s->yn[i] > 0.0) ? 1.0 : 0.0;
+        nucon[i] += mi * bucon[i];
+        bx[inc_path[i]] += mi * bucon[i];
+        by[i] -= mi * bucon[i];
+      }
+    }
+    /* y-block: y'_i = x'_r + ucon_i - g_e, g_e = [W_e]_+ / (1 + n_e), W_e = ucap_e + sum(x' + ucon) - C_e */
+    for (int e = 0; e < E; ++e) {
+      int ne = lptr[e + 1] - lptr[e];
+      double bg = 0.0;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) {
+        int64_t i = linc[j];
+        bx[inc_path[i]] += by[i];
+        nucon[i] += by[i];
+        bg -= by[i];
+      }
+      double bW = (s->W[e] > 0.0 ? 1.0 : 0.0) * bg / (1 + ne);
+      nucap[e] += bW;
+      bC[e] -= bW;
+      for (int j = lptr[e]; j < lptr[e + 1]; ++j) {
+        int64_t i = linc[j];
+        bx[inc_path[i]] += bW;
+        nucon[i] += bW;
+      }
+    }
+    /* x-block: S_c = sum x'_r; x'_r = xi(a_r - h(S*)); S* root of F */
+    for (int c = 0; c < D; ++c) {
+      int r0 = demand_path_ptr[c], m = demand_path_ptr[c + 1] - r0;
+      for (int r = r0; r < r0 + m; ++r) bx[r] += bS[c];
+      double Sst = s->Sst[c];
+      double t = Sst - Dm[c] + s->udem[c];
+      double mh = t > 0.0 ? 1.0 : 0.0;
+      double pw = (alpha == 0.0) ? 1.0 : exp(-alpha * log(Sst));
+      double h = (t > 0.0 ? t : 0.0) - pw / beta;
+      double dh = mh + (alpha == 0.0 ? 0.0 : alpha * pw / (beta * Sst));
+      double sk = 0.0, bh = 0.0;
+      for (int r = r0; r < r0 + m; ++r) {
+        double ar = 0.0;
+        for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) ar += s->y[i] - s->ucon[i];
+        double b = ar - h;
+        int hi = b >= n_r[r] * s->uneg[r];
+        double kap = hi ? 1.0 / n_r[r] : 1.0 / (n_r[r] + 1);
+        double xu = hi ? 0.0 : 1.0 / (n_r[r] + 1);
+        sk += kap;
+        double bb = bx[r] * kap;
+        nuneg[r] += bx[r] * xu;
+        ba[r] = bb;
+        bh -= bb;
+      }
+      /* h(S*, D, udem) */
+      double bSst = bh * dh;
+      bD[c] -= bh * mh;
+      nudem[c] += bh * mh;
+      /* implicit root: mu = -bS* / F_S, F_S = -dh * sum kappa - 1 */
+      double FS = -dh * sk - 1.0;
+      double mu = -bSst / FS;
+      bD[c] += mu * sk * mh;
+      nudem[c] -= mu * sk * mh;
+      for (int r = r0; r < r0 + m; ++r) {
+        double ar = 0.0;
+        for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) ar += s->y[i] - s->ucon[i];
+        double b = ar - h;
+        int hi = b >= n_r[r] * s->uneg[r];
+        double kap = hi ? 1.0 / n_r[r] : 1.0 / (n_r[r] + 1);
+        double xu = hi ? 0.0 : 1.0 / (n_r[r] + 1);
+        ba[r] += mu * kap;
+        nuneg[r] += mu * xu;
+        /* a_r = sum (y_i - ucon_i) */
+        for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) {
+          nby[i] += ba[r];
+          nucon[i] -= ba[r];
+        }
+      }
+    }
+    /* the inputs of sweep k become the outputs of sweep k-1 */
+    memset(bx, 0, sizeof(double) * (size_t)P); /* x^k is not an input of the full-form sweep */
+    memcpy(by, nby, sizeof(double) * (size_t)nnz);
+    memcpy(bucon, nucon, sizeof(double) * (size_t)nnz);
+    memcpy(bucap, nucap, sizeof(double) * (size_t)E);
+    memcpy(budem, nudem, sizeof(double) * (size_t)D);
+    memcpy(buneg, nuneg, sizeof(double) * (size_t)P);
+  }
+  /* initial point: y^0_i = D_c / |P_c| for the incidences of the paths of c */
+  for (int c = 0; c < D; ++c) {
+    int m = demand_path_ptr[c + 1] - demand_path_ptr[c];
+    for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r)
+      for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) bD[c] += by[i] / m;
+  }
+  for (int e = 0; e < E; ++e) dC[e] = bC[e];
+  for (int c = 0; c < D; ++c) dD[c] = bD[c];
+  for (int k = 0; k < K; ++k) {
+    free(sw[k].y); free(sw[k].ucon); free(sw[k].ucap); free(sw[k].udem); free(sw[k].uneg);
+    free(sw[k].x); free(sw[k].Sst); free(sw[k].S); free(sw[k].g); free(sw[k].W); free(sw[k].yn);
+  }
+#undef ALLOC
+  free(sw); free(y); free(ucon); free(ucap); free(udem); free(uneg); free(Sws); free(a);
+  free(bx); free(by); free(bucon); free(bucap); free(budem); free(buneg); free(bC); free(bD);
+  free(nby); free(nucon); free(nucap); free(nudem); free(nuneg); free(bS); free(ba);
+  free(C); free(Dm); free(n_r); free(dem_of); free(lptr); free(fill); free(linc); free(inc_path);
+  return 0;
+}

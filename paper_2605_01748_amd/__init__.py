@@ -21,7 +21,7 @@ TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
 ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
-       "te_solve_batch", "te_destroy", "te_destroy_batch", "te_info", "te_last_error"]
+       "te_solve_batch", "te_kernel_times", "te_destroy", "te_destroy_batch", "te_info", "te_last_error"]
 
 
 class TEError(RuntimeError):
@@ -80,6 +80,8 @@ def library(path: str = LIB_PATH):
     lib.te_create_batch.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(P)]
     lib.te_solve_batch.restype = I
     lib.te_solve_batch.argtypes = [P, ctypes.POINTER(_Options), P, P, P, P]
+    lib.te_kernel_times.restype = I
+    lib.te_kernel_times.argtypes = [P, ctypes.POINTER(_Options), P, I, P]
     lib.te_destroy.restype = None
     lib.te_destroy.argtypes = [P]
     lib.te_destroy_batch.restype = None
@@ -214,6 +216,17 @@ class Problem:
                                   ctypes.byref(st) if st is not None else None))
         del keep
         return x_out, S_out, (st.as_dict() if st is not None else None)
+
+    def kernel_times(self, opts: Options | None = None, iters: int = 64, stream=None):
+        """Mean device time (ms) of the graph engine's demand and link kernels over `iters` iterations."""
+        import torch
+        opts = opts or Options()
+        o, keep = opts.to_c()
+        out = np.zeros(2)
+        sp = _stream_ptr(torch.device("cuda", self.device)) if stream is None else stream
+        _check(library().te_kernel_times(self._h, ctypes.byref(o), sp, iters, out.ctypes.data))
+        del keep
+        return float(out[0]), float(out[1])
 
     def close(self):
         if getattr(self, "_h", None):

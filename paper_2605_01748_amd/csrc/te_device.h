@@ -46,130 +46,134 @@ __device__ __forceinline__ double wave_max_d(double v) {
 // F(S) = sum_r xi_r(a_r - h(S)) - S (continuous, strictly decreasing) gives S, then x.
 // ------------------------------------------------------------------------------------------
 struct Lane {
-  float a;      // a_r
-  float un;     // u_neg_r (current beta scale)
-  float n;      // n_r
-  float rn;     // 1 / n_r
-  float rn1;    // 1 / (n_r + 1)
+  double a;     // a_r
+  double un;    // u_neg_r (current beta scale)
+  double n;     // n_r
+  double rn;    // 1 / n_r
+  double rn1;   // 1 / (n_r + 1)
   bool on;      // lane holds a path of the demand
 };
 
 struct Dem {
-  float D, u, alpha, binv;  // demand, u_dem (current scale), alpha, 1/beta
+  double D, u, binv;  // demand, u_dem (current scale), 1/beta
+  float alpha;
 };
 
-__device__ __forceinline__ float pow_neg_alpha(float S, float alpha) {
-  return alpha == 0.f ? 1.f : exp2f(-alpha * log2f(S));
+// S^-alpha in FP32: at the root the term's own slope alpha S^-alpha / (beta S) damps its rounding,
+// a relative error eps in it moves the root by at most eps / alpha relative.
+__device__ __forceinline__ double pow_neg_alpha(double S, float alpha) {
+  return alpha == 0.f ? 1.0 : (double)exp2f(-alpha * log2f((float)S));
 }
 
-__device__ __forceinline__ float xi_of(float b, const Lane &L) {
+__device__ __forceinline__ double xi_of(double b, const Lane &L) {
   return (b >= L.n * L.un) ? b * L.rn : (b + L.un) * L.rn1;
 }
 
-__device__ __forceinline__ float h_of(float S, const Dem &c) {
-  return fmaxf(S - c.D + c.u, 0.f) - pow_neg_alpha(S, c.alpha) * c.binv;
+__device__ __forceinline__ double h_of(double S, const Dem &c) {
+  return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, c.alpha) * c.binv;
 }
 
 // F(S) and F'(S) summed over the group (uniform inside the group).
-__device__ __forceinline__ void F_eval(float S, const Lane &L, const Dem &c, int G, float &F, float &dF) {
-  if (c.alpha > 0.f && !(S > 0.f)) {
+__device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, int G, double &F, double &dF) {
+  if (c.alpha > 0.f && !(S > 0.0)) {
     F = INFINITY;
     dF = -INFINITY;
     return;
   }
-  float t = S - c.D + c.u;
-  float pw = pow_neg_alpha(S, c.alpha);
-  float h = fmaxf(t, 0.f) - pw * c.binv;
-  float dh = (t > 0.f ? 1.f : 0.f) + (c.alpha > 0.f ? c.alpha * pw * c.binv / S : 0.f);
-  float b = L.a - h;
-  bool hi_branch = b >= L.n * L.un;
-  float v = L.on ? (hi_branch ? b * L.rn : (b + L.un) * L.rn1) : 0.f;
-  float dv = L.on ? (hi_branch ? L.rn : L.rn1) : 0.f;
-  v = group_sum(v, G);
-  dv = group_sum(dv, G);
+  const double t = S - c.D + c.u;
+  const double pw = pow_neg_alpha(S, c.alpha);
+  const double h = fmax(t, 0.0) - pw * c.binv;
+  const double dh = (t > 0.0 ? 1.0 : 0.0) + (c.alpha > 0.f ? (double)c.alpha * pw * c.binv / S : 0.0);
+  const double b = L.a - h;
+  const bool hi_branch = b >= L.n * L.un;
+  double v = L.on ? (hi_branch ? b * L.rn : (b + L.un) * L.rn1) : 0.0;
+  double dv = L.on ? (hi_branch ? L.rn : L.rn1) : 0.0;
+  v = group_sum_d(v, G);
+  dv = group_sum_d(dv, G);
   F = v - S;
-  dF = -dh * dv - 1.f;
+  dF = -dh * dv - 1.0;
 }
 
 // Safeguarded Newton (appendix B.2): bracket [lo, hi] with F(lo) > 0 > F(hi) grown from the
 // warm start, Newton steps while they stay inside, bisection otherwise.
-__device__ float sum_root(float S0, const Lane &L, const Dem &c, int G, int *steps) {
-  if (c.alpha > 0.f && !(S0 > 0.f)) S0 = fmaxf(c.D, 1e-6f);
-  float F0, d0;
+__device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *steps) {
+  if (c.alpha > 0.f && !(S0 > 0.0)) S0 = fmax(c.D, 1e-6);
+  double F0, d0;
   F_eval(S0, L, c, G, F0, d0);
   *steps = 0;
-  if (F0 == 0.f) return S0;
-  float lo, hi;
-  float Fs, dFs, S;
-  if (F0 > 0.f) {
+  if (F0 == 0.0) return S0;
+  double lo, hi, Fs, dFs, S;
+  if (F0 > 0.0) {
     lo = S0;
-    float Flo = F0, dlo = d0;
-    float step = fmaxf(fabsf(S0), 1e-6f);
+    double Flo = F0, dlo = d0;
+    double step = fmax(fabs(S0), 1e-6);
     hi = S0 + step;
-    for (int i = 0; i < 160; ++i) {
-      float Fh, dh;
+    for (int i = 0; i < 1100; ++i) {
+      double Fh, dh;
       hi = S0 + step;
       F_eval(hi, L, c, G, Fh, dh);
-      if (Fh == 0.f) return hi;
-      if (Fh < 0.f) break;
+      if (Fh == 0.0) return hi;
+      if (Fh < 0.0) break;
       lo = hi;
       Flo = Fh;
       dlo = dh;
-      step *= 2.f;
+      step *= 2.0;
     }
     S = lo;
     Fs = Flo;
     dFs = dlo;
   } else {
     hi = S0;
-    float Fhi = F0, dhi = d0;
+    double Fhi = F0, dhi = d0;
     if (c.alpha > 0.f) {
       lo = S0;
-      for (int i = 0; i < 160; ++i) {
-        float Fl, dl;
-        lo *= 0.5f;
+      for (int i = 0; i < 1100; ++i) {
+        double Fl, dl;
+        lo *= 0.5;
         F_eval(lo, L, c, G, Fl, dl);
-        if (Fl == 0.f) return lo;
-        if (Fl > 0.f) break;
+        if (Fl == 0.0) return lo;
+        if (Fl > 0.0) break;
         hi = lo;
         Fhi = Fl;
         dhi = dl;
       }
     } else {
-      float step = fmaxf(fabsf(S0), 1e-6f);
+      double step = fmax(fabs(S0), 1e-6);
       lo = S0 - step;
-      for (int i = 0; i < 160; ++i) {
-        float Fl, dl;
+      for (int i = 0; i < 1100; ++i) {
+        double Fl, dl;
         lo = S0 - step;
         F_eval(lo, L, c, G, Fl, dl);
-        if (Fl == 0.f) return lo;
-        if (Fl > 0.f) break;
+        if (Fl == 0.0) return lo;
+        if (Fl > 0.0) break;
         hi = lo;
         Fhi = Fl;
         dhi = dl;
-        step *= 2.f;
+        step *= 2.0;
       }
     }
     S = hi;
     Fs = Fhi;
     dFs = dhi;
   }
-  for (int it = 0; it < 64; ++it) {
-    float Sn = 0.f;
-    bool newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.f;
+  for (int it = 0; it < 100; ++it) {
+    double Sn = 0.0;
+    bool newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.0;
     if (newton) {
       Sn = S - Fs / dFs;
       newton = (Sn > lo && Sn < hi);
     }
-    if (!newton) Sn = 0.5f * (lo + hi);
-    float Fn, dn;
+    if (!newton) Sn = 0.5 * (lo + hi);
+    double Fn, dn;
     F_eval(Sn, L, c, G, Fn, dn);
     ++*steps;
-    if (Fn == 0.f) return Sn;
-    if (Fn > 0.f) lo = Sn; else hi = Sn;
-    float tol = 2.4e-7f * fmaxf(fabsf(Sn), 1e-30f);
+    if (Fn == 0.0) return Sn;
+    if (Fn > 0.0) lo = Sn; else hi = Sn;
+    // same criterion as the FP64 reference: 1e-13 relative above 1, absolute below (normalised
+    // units, where F's own rounding noise is ~1e-16 times its O(1) terms)
+    const double tol = 1e-13 * fmax(fabs(Sn), 1.0);
     if (hi - lo <= tol) return Sn;
-    if (newton && fabsf(Sn - S) <= tol) return Sn;
+    if (newton && fabs(Sn - S) <= tol) return Sn;
     S = Sn;
     Fs = Fn;
     dFs = dn;

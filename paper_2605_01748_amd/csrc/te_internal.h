@@ -48,20 +48,28 @@ struct Prob {
   const int32_t *lpaths;   // [nnz] path of each CSC entry (link-major, path-ascending)
   const float *Dn;         // [D] demand
   const double *Cn;        // [E] capacity
+  // link kernel work split: non-empty links in order (nzlink), their CSC starts (nzptr, one more
+  // entry at the end), per-workgroup ranges of non-empty-link ranks (blk[nB+1]); lpf = lpaths
+  // with bit 31 set on the first entry of every link
+  const int32_t *lpf;
+  const int32_t *nzlink;
+  const int32_t *nzptr;
+  const int32_t *blk;
 };
 
 // Iteration state on the device.
 struct State {
-  float *x, *uneg;   // [P] path rates and non-negativity duals
-  float *udem, *S;   // [D] demand duals and last root of the sum equation
-  float2 *gq;        // [E] (g, q): g = capacity / consensus dual, q = consensus offset
+  float *x, *uneg;   // [P] path rates and non-negativity duals (FP32: the bulk of the state)
+  double *udem, *S;  // [D] demand duals and last root of the sum equation
+  double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
   Ctrl *ctrl;        // [2]
   double *partA;     // [2][nA][4]
   double *partB;     // [2][nB][4]
   int32_t nA, nB;
 };
 
-constexpr int kLinkBlocks = 128;     // workgroups of the link kernel (partB rows)
+constexpr int kMaxLinkBlocks = 512;  // workgroups of the link kernel (partB rows), at most
+constexpr int kMaxLinksPerBlock = 1024;
 constexpr int kThreads = 256;        // threads per workgroup of the graph-engine kernels
 constexpr int kBlockThreads = 1024;  // threads of the workgroup engine
 

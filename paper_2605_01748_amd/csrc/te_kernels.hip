@@ -22,30 +22,37 @@
 namespace te {
 
 // ------------------------------------------------------------------------------------------
-// control record of this iteration, identical in every workgroup
+// control record of this iteration, identical in every workgroup.  Wave 0 prefetches the
+// previous record and its partial sums (prefetch_ctrl) before the workgroup's gathers and
+// applies the decision afterwards (finish_ctrl), so the loads overlap with the gathers.
 // ------------------------------------------------------------------------------------------
-__device__ void current_ctrl(const State &s, const Params &prm, int par, Ctrl *out) {
-  // par = k & 1 of this iteration; the record of iteration k-1 and its partial sums live in slot par^1
-  if (threadIdx.x < 64) {
-    const Ctrl prev = s.ctrl[par ^ 1];
-    double v[4] = {0.0, 0.0, 0.0, -INFINITY};
-    v[2] = -INFINITY;
-    if (prev.pending) {
-      const double *pb = s.partB + (size_t)(par ^ 1) * s.nB * 4;
-      for (int i = threadIdx.x; i < s.nB; i += 64) {
-        v[0] += pb[4 * i + 0];
-        v[1] += pb[4 * i + 1];
-        v[2] = fmax(v[2], pb[4 * i + 2]);
-        v[3] = fmax(v[3], pb[4 * i + 3]);
-      }
-      v[0] = wave_sum_d(v[0]);
-      v[1] = wave_sum_d(v[1]);
-      v[2] = wave_max_d(v[2]);
-      v[3] = wave_max_d(v[3]);
-    }
-    if (threadIdx.x == 0) *out = decide(prev, v, prm);
+struct CtrlPrefetch {
+  Ctrl prev;
+  double v[4];
+};
+
+__device__ __forceinline__ void prefetch_ctrl(const State &s, int par, CtrlPrefetch &cp) {
+  // par = k & 1 of this iteration; record k-1 and its partial sums live in slot par^1
+  cp.prev = s.ctrl[par ^ 1];
+  cp.v[0] = 0.0;
+  cp.v[1] = 0.0;
+  cp.v[2] = -INFINITY;
+  cp.v[3] = -INFINITY;
+  const double *pb = s.partB + (size_t)(par ^ 1) * s.nB * 4;
+  for (int i = threadIdx.x; i < s.nB; i += 64) {
+    cp.v[0] += pb[4 * i + 0];
+    cp.v[1] += pb[4 * i + 1];
+    cp.v[2] = fmax(cp.v[2], pb[4 * i + 2]);
+    cp.v[3] = fmax(cp.v[3], pb[4 * i + 3]);
   }
-  __syncthreads();
+}
+
+__device__ __forceinline__ void finish_ctrl(CtrlPrefetch &cp, const Params &prm, Ctrl *out) {
+  cp.v[0] = wave_sum_d(cp.v[0]);
+  cp.v[1] = wave_sum_d(cp.v[1]);
+  cp.v[2] = wave_max_d(cp.v[2]);
+  cp.v[3] = wave_max_d(cp.v[3]);
+  if (threadIdx.x == 0) *out = decide(cp.prev, cp.v, prm);
 }
 
 // block-wide reduction of 4 partials (sum, sum, max, max) into dst[0..3] by thread 0
@@ -94,10 +101,10 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, flo
       s.uneg[r] = 0.f;
       sum += v;
     }
-    s.udem[c] = 0.f;
-    s.S[c] = sum;
+    s.udem[c] = 0.0;
+    s.S[c] = (double)sum;
   }
-  for (int e = tid; e < p.E; e += nth) s.gq[e] = make_float2(0.f, 0.f);
+  for (int e = tid; e < p.E; e += nth) s.gq[e] = make_double2(0.0, 0.0);
   if (tid == 0) {
     Ctrl c = initial_ctrl(prm);
     s.ctrl[1] = c;   // read as "iteration -1" by iteration 0, not pending
@@ -112,61 +119,73 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, flo
 __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
-  current_ctrl(s, prm, par, &cs);
-  if (cs.stop) return;
-  const float inv_f = (float)cs.inv_f;
+  CtrlPrefetch cp;
+  if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
   const int G = p.G;
   const int t = threadIdx.x;
   const int lane = t & (G - 1);
   const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
-  double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
+  // gathers (independent of the control record): sums of g and q along the path
+  int r0 = 0, np = 0, r = 0, n = 1;
+  float xr = 0.f, ung = 0.f, Dc = 0.f;
+  double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
+  bool on = false;
   if (c < p.D) {
-    const int r0 = p.dptr[c], np = p.dptr[c + 1] - r0;
-    Lane L;
-    L.on = lane < np;
-    const int r = r0 + (L.on ? lane : 0);
-    float xr = 0.f;
-    int n = 1;
-    L.a = 0.f;
-    L.un = 0.f;
-    if (L.on) {
+    r0 = p.dptr[c];
+    np = p.dptr[c + 1] - r0;
+    on = lane < np;
+    r = r0 + (on ? lane : 0);
+    if (on) {
       const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
       n = i1 - i0;
-      float G_r = 0.f;
       for (int i = i0; i < i1; ++i) {
-        const float2 v = s.gq[p.plinks[i]];
-        G_r += v.x * inv_f - v.y;
+        const double2 v = s.gq[p.plinks[i]];
+        sg += v.x;
+        sq += v.y;
       }
       xr = s.x[r];
-      L.a = (float)n * xr - G_r;
-      L.un = s.uneg[r] * inv_f;
+      ung = s.uneg[r];
     }
-    L.n = (float)n;
-    L.rn = 1.f / (float)n;
-    L.rn1 = 1.f / (float)(n + 1);
+    Dc = p.Dn[c];
+    udc = s.udem[c];
+    S0 = s.S[c];
+  }
+  if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
+  __syncthreads();
+  if (cs.stop) return;
+  const double inv_f = cs.inv_f;
+  double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
+  if (c < p.D) {
+    Lane L;
+    L.on = on;
+    L.a = on ? (double)n * (double)xr - (sg * inv_f - sq) : 0.0;
+    L.un = (double)ung * inv_f;
+    L.n = (double)n;
+    L.rn = 1.0 / (double)n;
+    L.rn1 = 1.0 / (double)(n + 1);
     Dem dm;
-    dm.D = p.Dn[c];
-    dm.u = s.udem[c] * inv_f;
+    dm.D = (double)Dc;
+    dm.u = udc * inv_f;
     dm.alpha = (float)cs.alpha;
-    dm.binv = (float)(1.0 / cs.beta);
+    dm.binv = 1.0 / cs.beta;
     int steps;
-    const float Sst = sum_root(s.S[c], L, dm, G, &steps);
-    const float h = h_of(Sst, dm);
-    const float xn = L.on ? xi_of(L.a - h, L) : 0.f;
-    const float Ssum = group_sum(xn, G);
+    const double Sst = sum_root(S0, L, dm, G, &steps);
+    const double h = h_of(Sst, dm);
+    const float xn = L.on ? (float)xi_of(L.a - h, L) : 0.f;
+    const double Ssum = group_sum_d((double)xn, G);
     if (L.on) {
-      const float un = fmaxf(L.un - xn, 0.f);
+      const float un = (float)fmax(L.un - (double)xn, 0.0);
       s.x[r] = xn;
       s.uneg[r] = un;
       ds2 = (double)(xn - xr) * (double)(xn - xr);
-      dr2 = (double)(un - L.un) * (double)(un - L.un);
+      dr2 = ((double)un - L.un) * ((double)un - L.un);
     }
     if (lane == 0) {
-      const float ud = fmaxf(dm.u + Ssum - dm.D, 0.f);
+      const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
       s.udem[c] = ud;
       s.S[c] = Sst;
-      dr2 += (double)(ud - dm.u) * (double)(ud - dm.u);
-      dem_v = ((double)Ssum - (double)dm.D) / (double)dm.D;
+      dr2 += (ud - dm.u) * (ud - dm.u);
+      dem_v = (Ssum - dm.D) / dm.D;
     }
   }
   block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
@@ -174,38 +193,75 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
 
 // ------------------------------------------------------------------------------------------
 // Step a3 + a4: link loads by segmented FP64 sums over the CSC lists, capacity/consensus duals.
-// Also folds a slice of the demand kernel's partial sums into this workgroup's row.
+// Workgroup b owns a contiguous range of non-empty links holding ~nnz/nB CSC entries; each
+// wavefront walks a contiguous part of it in coalesced rows of 64 entries, reduces runs of equal
+// link inside the row with a segmented scan and adds one partial per run into an LDS FP64
+// accumulator.  Also folds a slice of the demand kernel's partial sums into its row.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_link(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
-  current_ctrl(s, prm, par, &cs);
+  __shared__ double acc[kMaxLinksPerBlock];
+  CtrlPrefetch cp;
+  if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
+  for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
+  __syncthreads();
+  const int j0 = p.nzptr[k0], j1 = p.nzptr[k1];
+  const int len = j1 - j0, per = (len + nw - 1) / nw;
+  const int ja = j0 + min(len, w * per), jb = j0 + min(len, (w + 1) * per);
+  if (ja < jb) {
+    // rank of the link holding entry ja
+    int lo = k0, hi = k1 - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (p.nzptr[mid] <= ja) lo = mid; else hi = mid - 1;
+    }
+    int kbase = lo;
+    for (int j = ja; j < jb; j += 64) {
+      const int jj = j + lane;
+      const bool valid = jj < jb;
+      const int32_t v = valid ? p.lpf[jj] : 0;
+      const bool head = valid && v < 0 && jj != ja;
+      const uint64_t hm = __ballot(head);
+      const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int rank = kbase + __popcll(hm & le);
+      double val = valid ? (double)s.x[v & 0x7fffffff] : 0.0;
+      for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(val, d, 64);
+        const int ry = __shfl_up(rank, d, 64);
+        if (lane >= d && ry == rank) val += y;
+      }
+      const int rn = __shfl_down(rank, 1, 64);
+      const int vn = __shfl_down(valid ? 1 : 0, 1, 64);
+      const bool tail = valid && (lane == 63 || !vn || rn != rank);
+      if (tail) atomicAdd(&acc[rank - k0], val);
+      kbase += __popcll(hm);
+    }
+  }
+  if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
+  __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctrl w = cs;
-    w.pending = cs.stop ? 0 : 1;
-    s.ctrl[par] = w;
+    Ctrl wr = cs;
+    wr.pending = cs.stop ? 0 : 1;
+    s.ctrl[par] = wr;
   }
   if (cs.stop) return;
   const double inv_f = cs.inv_f;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
   double dr2 = 0.0, cap_v = -INFINITY;
-  for (int e = blockIdx.x * nw + w; e < p.E; e += gridDim.x * nw) {
-    const int j0 = p.lptr[e], j1 = p.lptr[e + 1];
-    double acc = 0.0;
-    for (int j = j0 + lane; j < j1; j += 64) acc += (double)s.x[p.lpaths[j]];
-    acc = wave_sum_d(acc);
-    if (lane == 0) {
-      const float2 v = s.gq[e];
-      const float gold = (float)((double)v.x * inv_f);
-      const int ne = j1 - j0;
-      const double Ce = p.Cn[e];
-      double g = (double)gold + (acc - Ce) / (double)(1 + ne);
-      const float gn = (float)fmax(g, 0.0);
-      s.gq[e] = make_float2(gn, gold - gn);
-      dr2 += (double)(1 + ne) * (double)(gn - gold) * (double)(gn - gold);
-      if (ne > 0) cap_v = fmax(cap_v, (acc - Ce) / Ce);
-    }
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const int e = p.nzlink[k];
+    const double load = acc[k - k0];
+    const int ne = p.nzptr[k + 1] - p.nzptr[k];
+    const double2 v = s.gq[e];
+    const double gold = v.x * inv_f;
+    const double Ce = p.Cn[e];
+    const double gn = fmax(gold + (load - Ce) / (double)(1 + ne), 0.0);
+    s.gq[e] = make_double2(gn, gold - gn);
+    dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
+    cap_v = fmax(cap_v, (load - Ce) / Ce);
   }
   // fold the demand kernel's rows b, b + nB, ... (fixed order)
   double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
@@ -324,14 +380,56 @@ __global__ void kp_demand_trim(Prob p, ProjBuf b) {
 // all their rate, the path at K* the remainder; a path trimmed by several links keeps the max.
 __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
   __shared__ double red[4];
+  __shared__ uint64_t kred[4];
+  __shared__ double xred[4];
   __shared__ uint64_t keyT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int e = blockIdx.x; e < p.E; e += gridDim.x) {
     const double V = b.L[e] - p.Cn[e];
     if (!(V > 0.0)) continue;  // uniform in the workgroup
     const int j0 = p.lptr[e], j1 = p.lptr[e + 1];
-    // f(T) = sum of x over incidences with key >= T; find the largest T with f(T) >= V
-    uint64_t lo = 0ull, hi = ~0ull;  // invariant: f(lo) >= V, f(hi + 1) < V region search
-    // binary search on [lo, hi]
+    // fast path: the path with the largest key usually absorbs the whole violation
+    uint64_t km = 0ull;
+    double xm = 0.0;
+    for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+      const int r = p.lpaths[j];
+      const uint64_t k = trim_key(b.lsc[r], r);
+      if (k > km) {
+        km = k;
+        xm = b.xd[r];
+      }
+    }
+    for (int m = 1; m < 64; m <<= 1) {
+      const uint64_t ko = __shfl_xor(km, m, 64);
+      const double xo = __shfl_xor(xm, m, 64);
+      if (ko > km) {
+        km = ko;
+        xm = xo;
+      }
+    }
+    if (lane == 0) {
+      kred[w] = km;
+      xred[w] = xm;
+    }
+    __syncthreads();
+    km = kred[0];
+    xm = xred[0];
+    for (int i = 1; i < 4; ++i)
+      if (kred[i] > km) {
+        km = kred[i];
+        xm = xred[i];
+      }
+    __syncthreads();
+    if (xm >= V) {
+      if (threadIdx.x == 0) {
+        const int r = (int)(uint32_t)(km & 0xffffffffull);
+        atomicMax((unsigned long long *)&b.trim[r], (unsigned long long)__double_as_longlong(V));
+      }
+      continue;
+    }
+    // general case: threshold key K* where the descending cumulative rate reaches V,
+    // f(T) = sum of x over incidences with key >= T; the largest T with f(T) >= V
+    uint64_t lo = 0ull, hi = ~0ull;
     for (int bit = 0; bit < 64; ++bit) {
       const uint64_t mid = lo + ((hi - lo) >> 1) + ((hi - lo) & 1ull);
       double acc = 0.0;
@@ -340,7 +438,7 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
         if (trim_key(b.lsc[r], r) >= mid) acc += b.xd[r];
       }
       acc = wave_sum_d(acc);
-      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+      if (lane == 0) red[w] = acc;
       __syncthreads();
       const double f = red[0] + red[1] + red[2] + red[3];
       __syncthreads();
@@ -350,14 +448,13 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
     if (threadIdx.x == 0) keyT = lo;
     __syncthreads();
     const uint64_t T = keyT;
-    // rate strictly above the threshold key
     double acc = 0.0;
     for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
       const int r = p.lpaths[j];
       if (trim_key(b.lsc[r], r) > T) acc += b.xd[r];
     }
     acc = wave_sum_d(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    if (lane == 0) red[w] = acc;
     __syncthreads();
     const double above = red[0] + red[1] + red[2] + red[3];
     __syncthreads();
@@ -408,14 +505,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   const BatchDesc d = descs[blockIdx.x];
   const int E = d.E, P = d.P, D = d.D, nnz = d.nnz, G = d.G, logG = d.logG;
   // LDS layout
-  double *Cn = (double *)smem;                       // E
+  double2 *gq = (double2 *)smem;                     // E
+  double *Cn = (double *)(gq + E);                   // E
   double *Lx = Cn + E;                               // E  (loads, FP64)
-  float2 *gq = (float2 *)(Lx + E);                   // E
-  float *x = (float *)(gq + E);                      // P
+  double *udem = Lx + E;                             // D
+  double *S = udem + D;                              // D
+  float *x = (float *)(S + D);                       // P
   float *uneg = x + P;                               // P
-  float *udem = uneg + P;                            // D
-  float *S = udem + D;                               // D
-  float *Dn = S + D;                                 // D
+  float *Dn = uneg + P;                              // D
   int32_t *pptr = (int32_t *)(Dn + D);               // P + 1
   int32_t *plinks = pptr + P + 1;                    // nnz
   int32_t *dptr = plinks + nnz;                      // D + 1
@@ -430,7 +527,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   for (int i = tid; i < nnz; i += nth) lpaths[i] = gi[d.off_lpaths + i];
   for (int i = tid; i < E; i += nth) {
     Cn[i] = pools.Cn[d.off_E + i];
-    gq[i] = make_float2(0.f, 0.f);
+    gq[i] = make_double2(0.0, 0.0);
   }
   for (int i = tid; i < D; i += nth) Dn[i] = pools.Dn[d.off_D + i];
   __syncthreads();
@@ -444,8 +541,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
       uneg[r] = 0.f;
       sum += v;
     }
-    udem[c] = 0.f;
-    S[c] = sum;
+    udem[c] = 0.0;
+    S[c] = (double)sum;
   }
   if (tid == 0) cs = initial_ctrl(prm);
   __syncthreads();
@@ -454,10 +551,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   const int groups = nth >> logG;
   const int w = tid >> 6, l64 = tid & 63, nw = nth >> 6;
   while (!cs.stop) {
-    const float inv_f = (float)cs.inv_f;
+    const double inv_f = cs.inv_f;
     Dem dm;
     dm.alpha = (float)cs.alpha;
-    dm.binv = (float)(1.0 / cs.beta);
+    dm.binv = 1.0 / cs.beta;
     double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY, cap_v = -INFINITY;
     // demand step
     for (int c0 = 0; c0 < D; c0 += groups) {
@@ -469,43 +566,44 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
         const int r = r0 + (L.on ? lane : 0);
         float xr = 0.f;
         int n = 1;
-        L.a = 0.f;
-        L.un = 0.f;
+        L.a = 0.0;
+        L.un = 0.0;
         if (L.on) {
           const int i0 = pptr[r], i1 = pptr[r + 1];
           n = i1 - i0;
-          float G_r = 0.f;
+          double sg = 0.0, sq = 0.0;
           for (int i = i0; i < i1; ++i) {
-            const float2 v = gq[plinks[i]];
-            G_r += v.x * inv_f - v.y;
+            const double2 v = gq[plinks[i]];
+            sg += v.x;
+            sq += v.y;
           }
           xr = x[r];
-          L.a = (float)n * xr - G_r;
-          L.un = uneg[r] * inv_f;
+          L.a = (double)n * (double)xr - (sg * inv_f - sq);
+          L.un = (double)uneg[r] * inv_f;
         }
-        L.n = (float)n;
-        L.rn = 1.f / (float)n;
-        L.rn1 = 1.f / (float)(n + 1);
-        dm.D = Dn[c];
+        L.n = (double)n;
+        L.rn = 1.0 / (double)n;
+        L.rn1 = 1.0 / (double)(n + 1);
+        dm.D = (double)Dn[c];
         dm.u = udem[c] * inv_f;
         int steps;
-        const float Sst = sum_root(S[c], L, dm, G, &steps);
-        const float h = h_of(Sst, dm);
-        const float xn = L.on ? xi_of(L.a - h, L) : 0.f;
-        const float Ssum = group_sum(xn, G);
+        const double Sst = sum_root(S[c], L, dm, G, &steps);
+        const double h = h_of(Sst, dm);
+        const float xn = L.on ? (float)xi_of(L.a - h, L) : 0.f;
+        const double Ssum = group_sum_d((double)xn, G);
         if (L.on) {
-          const float un = fmaxf(L.un - xn, 0.f);
+          const float un = (float)fmax(L.un - (double)xn, 0.0);
           x[r] = xn;
           uneg[r] = un;
           ds2 += (double)(xn - xr) * (double)(xn - xr);
-          dr2 += (double)(un - L.un) * (double)(un - L.un);
+          dr2 += ((double)un - L.un) * ((double)un - L.un);
         }
         if (lane == 0) {
-          const float ud = fmaxf(dm.u + Ssum - dm.D, 0.f);
+          const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
           udem[c] = ud;
           S[c] = Sst;
-          dr2 += (double)(ud - dm.u) * (double)(ud - dm.u);
-          dem_v = fmax(dem_v, ((double)Ssum - (double)dm.D) / (double)dm.D);
+          dr2 += (ud - dm.u) * (ud - dm.u);
+          dem_v = fmax(dem_v, (Ssum - dm.D) / dm.D);
         }
       }
     }
@@ -516,15 +614,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
       double acc = 0.0;
       for (int j = j0 + l64; j < j1; j += 64) acc += (double)x[lpaths[j]];
       acc = wave_sum_d(acc);
-      if (l64 == 0) {
-        const float2 v = gq[e];
-        const float gold = (float)((double)v.x * (double)cs.inv_f);
+      if (l64 == 0 && j1 > j0) {
+        const double2 v = gq[e];
+        const double gold = v.x * inv_f;
         const int ne = j1 - j0;
-        const double g = (double)gold + (acc - Cn[e]) / (double)(1 + ne);
-        const float gn = (float)fmax(g, 0.0);
-        gq[e] = make_float2(gn, gold - gn);
-        dr2 += (double)(1 + ne) * (double)(gn - gold) * (double)(gn - gold);
-        if (ne > 0) cap_v = fmax(cap_v, (acc - Cn[e]) / Cn[e]);
+        const double gn = fmax(gold + (acc - Cn[e]) / (double)(1 + ne), 0.0);
+        gq[e] = make_double2(gn, gold - gn);
+        dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
+        cap_v = fmax(cap_v, (acc - Cn[e]) / Cn[e]);
       }
     }
     // partial sums and decision
@@ -667,6 +764,16 @@ hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, in
   return hipGetLastError();
 }
 
+hipError_t launch_demand(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
+  hipLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
+  return hipGetLastError();
+}
+
+hipError_t launch_link(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
+  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kThreads), 0, st, p, s, prm, par);
+  return hipGetLastError();
+}
+
 hipError_t launch_finish(const State &s, const Params *prm, int last_par, hipStream_t st) {
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, s, prm, last_par);
   return hipGetLastError();
@@ -701,7 +808,7 @@ hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools,
 }
 
 size_t block_lds_bytes(int E, int P, int D, int nnz) {
-  return (size_t)E * (8 + 8 + 8) + (size_t)P * 4 * 2 + (size_t)D * 4 * 3 +
+  return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 4) + (size_t)P * 4 * 2 +
          (size_t)4 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz) + 16;
 }
 

@@ -20,6 +20,8 @@
 namespace te {
 hipError_t launch_init(const Prob &, const State &, const Params *, const float *, float, hipStream_t);
 hipError_t launch_iteration(const Prob &, const State &, const Params *, int, hipStream_t);
+hipError_t launch_demand(const Prob &, const State &, const Params *, int, hipStream_t);
+hipError_t launch_link(const Prob &, const State &, const Params *, int, hipStream_t);
 hipError_t launch_finish(const State &, const Params *, int, hipStream_t);
 hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *, float *, double, int, hipStream_t);
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
@@ -65,6 +67,7 @@ struct te_ctx {
   double scale = 1.0;
   // host layout (kept for batches and updates)
   std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
+  std::vector<int32_t> lpf, nzlink, nzptr, blk;  // link-kernel work split
   std::vector<double> cap, dem;  // caller units
   std::vector<float> Dn;
   std::vector<double> Cn;
@@ -337,6 +340,35 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     for (int32_t r = 0; r < n_paths; ++r)
       for (int32_t i = c->pptr[r]; i < c->pptr[r + 1]; ++i) c->lpaths[fill[c->plinks[i]]++] = r;
   }
+  // link-kernel work split: workgroups own contiguous runs of non-empty links of ~nnz/nB entries
+  c->lpf = c->lpaths;
+  for (int32_t e = 0; e < n_links; ++e) {
+    if (c->lptr[e + 1] > c->lptr[e]) {
+      c->lpf[c->lptr[e]] |= (int32_t)0x80000000u;
+      c->nzlink.push_back(e);
+      c->nzptr.push_back(c->lptr[e]);
+    }
+  }
+  c->nzptr.push_back(c->nnz);
+  {
+    const int64_t want = std::min<int64_t>(kMaxLinkBlocks, std::max<int64_t>(1, (c->nnz + 4095) / 4096));
+    const int64_t target = std::max<int64_t>(1, (c->nnz + want - 1) / want);
+    int64_t cur = 0;
+    int cnt = 0;
+    c->blk.push_back(0);
+    for (size_t k = 0; k < c->nzlink.size(); ++k) {
+      const int64_t d = c->nzptr[k + 1] - c->nzptr[k];
+      if (cnt > 0 && (cur + d > target || cnt == kMaxLinksPerBlock)) {
+        c->blk.push_back((int32_t)k);
+        cur = 0;
+        cnt = 0;
+      }
+      cur += d;
+      ++cnt;
+    }
+    c->blk.push_back((int32_t)c->nzlink.size());
+  }
+  const int nB = (int)c->blk.size() - 1;
   c->maxp = 0;
   for (int32_t k = 0; k < n_demands; ++k) c->maxp = std::max(c->maxp, c->dptr[k + 1] - c->dptr[k]);
   c->G = 1;
@@ -354,14 +386,15 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   };
   if (hipSetDevice(hip_device) != hipSuccess) return cleanup_fail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
   // index pool: pptr | plinks | dptr | lptr | lpaths
-  const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz;
+  const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz + c->nnz + c->nzlink.size() +
+                    c->nzptr.size() + c->blk.size();
   const int nA = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
             dalloc(&c->d_Cn, c->E) == hipSuccess && dalloc(&c->st.x, c->P) == hipSuccess &&
             dalloc(&c->st.uneg, c->P) == hipSuccess && dalloc(&c->st.udem, c->D) == hipSuccess &&
             dalloc(&c->st.S, c->D) == hipSuccess && dalloc(&c->st.gq, c->E) == hipSuccess &&
             dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA * 4) == hipSuccess &&
-            dalloc(&c->st.partB, (size_t)2 * kLinkBlocks * 4) == hipSuccess &&
+            dalloc(&c->st.partB, (size_t)2 * nB * 4) == hipSuccess &&
             dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
             dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
             dalloc(&c->pb.lsc, c->P) == hipSuccess && dalloc(&c->pb.trim, c->P) == hipSuccess &&
@@ -376,7 +409,7 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
       hipEventCreate(&c->pe[1]) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "event creation failed"));
   c->st.nA = nA;
-  c->st.nB = kLinkBlocks;
+  c->st.nB = nB;
   {
     std::vector<int32_t> pool;
     pool.reserve(ni);
@@ -385,6 +418,10 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     pool.insert(pool.end(), c->dptr.begin(), c->dptr.end());
     pool.insert(pool.end(), c->lptr.begin(), c->lptr.end());
     pool.insert(pool.end(), c->lpaths.begin(), c->lpaths.end());
+    pool.insert(pool.end(), c->lpf.begin(), c->lpf.end());
+    pool.insert(pool.end(), c->nzlink.begin(), c->nzlink.end());
+    pool.insert(pool.end(), c->nzptr.begin(), c->nzptr.end());
+    pool.insert(pool.end(), c->blk.begin(), c->blk.end());
     if (hipMemcpy(c->d_i32, pool.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice) != hipSuccess)
       return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the index pool failed"));
   }
@@ -402,6 +439,10 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.dptr = p.plinks + c->nnz;
   p.lptr = p.dptr + c->D + 1;
   p.lpaths = p.lptr + c->E + 1;
+  p.lpf = p.lpaths + c->nnz;
+  p.nzlink = p.lpf + c->nnz;
+  p.nzptr = p.nzlink + c->nzlink.size();
+  p.blk = p.nzptr + c->nzptr.size();
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -514,6 +555,49 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
+  return TE_OK;
+}
+
+te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, int32_t iters, double *ms_out) {
+  if (!c || !ms_out) return fail(TE_ERR_INVALID, "null handle or output");
+  if (iters < 1 || iters > 4096) return fail(TE_ERR_INVALID, "iters must be in 1..4096");
+  te_options o;
+  if (opt) o = *opt; else te_default_options(&o);
+  o.fixed_iters = iters;
+  te_status s = check_options(&o);
+  if (s != TE_OK) return s;
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(c->device));
+  s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
+  if (s != TE_OK) return s;
+  std::vector<hipEvent_t> ev(3 * (size_t)iters, nullptr);
+  for (auto &e : ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto &f : ev)
+        if (f) (void)hipEventDestroy(f);
+      return fail(TE_ERR_DEVICE, "event creation failed");
+    }
+  hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, (float)(1.0 / c->scale), stream);
+  for (int k = 0; k < iters && err == hipSuccess; ++k) {
+    err = hipEventRecord(ev[3 * k], stream);
+    if (err == hipSuccess) err = launch_demand(c->prob, c->st, c->d_params, k & 1, stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 1], stream);
+    if (err == hipSuccess) err = launch_link(c->prob, c->st, c->d_params, k & 1, stream);
+    if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 2], stream);
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  double sd = 0.0, sl = 0.0;
+  for (int k = 0; k < iters && err == hipSuccess; ++k) {
+    float a = 0.f, b = 0.f;
+    err = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+    sd += a;
+    sl += b;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (err != hipSuccess) return fail(TE_ERR_DEVICE, "kernel timing: %s", hipGetErrorString(err));
+  ms_out[0] = sd / iters;
+  ms_out[1] = sl / iters;
   return TE_OK;
 }
 
