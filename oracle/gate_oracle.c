@@ -175,10 +175,13 @@ static double sum_root(const commodity_t *c, double S0, int max_steps, int *step
   double F0 = F_of(c, S0);
   *steps = 0;
   if (F0 == 0.0) return S0;
+  const double d0 = dF_of(c, S0);
+  /* first trial end of the bracket: 1.5 Newton steps from the warm start, then doubling */
+  double guess = (isfinite(F0) && isfinite(d0) && d0 < 0.0) ? -1.5 * F0 / d0 : 0.0;
   double lo, hi;
   if (F0 > 0.0) {
     lo = S0;
-    double step = fabs(S0) > 1e-6 ? fabs(S0) : 1e-6;
+    double step = guess > 0.0 ? guess : (fabs(S0) > 1e-6 ? fabs(S0) : 1e-6);
     for (;;) {
       hi = S0 + step;
       double Fh = F_of(c, hi);
@@ -190,17 +193,17 @@ static double sum_root(const commodity_t *c, double S0, int max_steps, int *step
   } else {
     hi = S0;
     if (c->alpha > 0.0) {
-      lo = S0;
+      lo = (guess < 0.0 && S0 + guess > 0.0) ? S0 + guess : 0.5 * S0;
       for (;;) {
-        lo *= 0.5;
         double Fl = F_of(c, lo);
         if (Fl == 0.0) return lo;
         if (Fl > 0.0) break;
         hi = lo;
+        lo *= 0.5;
         if (lo < 1e-300) return lo;
       }
     } else {
-      double step = fabs(S0) > 1e-6 ? fabs(S0) : 1e-6;
+      double step = guess < 0.0 ? -guess : (fabs(S0) > 1e-6 ? fabs(S0) : 1e-6);
       for (;;) {
         lo = S0 - step;
         double Fl = F_of(c, lo);
@@ -214,10 +217,13 @@ static double sum_root(const commodity_t *c, double S0, int max_steps, int *step
   double S = (F0 > 0.0) ? lo : hi;
   for (int it = 0; it < max_steps; ++it) {
     double Fs = F_of(c, S), dFs = dF_of(c, S);
+    double scale = fabs(S) > 1.0 ? fabs(S) : 1.0;
     double Sn = 0.0;
     int newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.0;
     if (newton) {
-      Sn = S - Fs / dFs;
+      double step = Fs / dFs;
+      if (fabs(step) <= tol * scale) return S - step; /* Newton correction below tolerance */
+      Sn = S - step;
       newton = (Sn > lo && Sn < hi);
     }
     if (!newton) Sn = 0.5 * (lo + hi);
@@ -225,9 +231,8 @@ static double sum_root(const commodity_t *c, double S0, int max_steps, int *step
     ++*steps;
     if (Fn == 0.0) return Sn;
     if (Fn > 0.0) lo = Sn; else hi = Sn;
-    double scale = fabs(Sn) > 1.0 ? fabs(Sn) : 1.0;
+    scale = fabs(Sn) > 1.0 ? fabs(Sn) : 1.0;
     if (hi - lo <= tol * scale) return Sn;
-    if (newton && fabs(Sn - S) <= tol * scale) return Sn;
     S = Sn;
   }
   return S;

@@ -217,6 +217,19 @@ class Problem:
         del keep
         return x_out, S_out, (st.as_dict() if st is not None else None)
 
+    def grad(self, dS, stream=None):
+        """Vector-Jacobian product through the last solve run with record=True (te_grad):
+        returns (dC [n_links], dD [n_demands]) float64 cuda tensors for the cotangent dS on the
+        unprojected per-demand sums."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        dS = dS.to(device=dev, dtype=torch.float32).contiguous()
+        dC = torch.empty(self.n_links, dtype=torch.float64, device=dev)
+        dD = torch.empty(self.n_demands, dtype=torch.float64, device=dev)
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_grad(self._h, sp, dS.data_ptr(), dC.data_ptr(), dD.data_ptr()))
+        return dC, dD
+
     def kernel_times(self, opts: Options | None = None, iters: int = 64, stream=None):
         """Mean device time (ms) of the graph engine's demand and link kernels over `iters` iterations."""
         import torch
@@ -280,3 +293,36 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class GateSolve(torch.autograd.Function):
+        """S^(K) = unprojected per-demand sums after K iterations, as a differentiable function of
+        the capacities C [n_links] and demands D [n_demands] (float64 CPU tensors, caller units).
+        Forward: te_update + te_solve(record, fixed_iters=K); backward: te_grad (adjoint kernels,
+        checkpoints every opts.ckpt_every iterations).  The (beta, alpha) schedule of the forward solve
+        and the unit scale are held fixed in the derivative."""
+
+        @staticmethod
+        def forward(ctx, problem, C, D, K, opts=None):
+            o = opts or Options()
+            o = Options(**{**o.__dict__, "fixed_iters": int(K), "record": True, "project": False})
+            problem.update(C.detach().cpu().numpy(), D.detach().cpu().numpy())
+            _, S, _ = problem.solve(o, stats=False)
+            ctx.problem = problem
+            return S.clone()
+
+        @staticmethod
+        def backward(ctx, gS):
+            dC, dD = ctx.problem.grad(gS)
+            return None, dC.cpu(), dD.cpu(), None, None
+
+    return GateSolve
+
+
+def __getattr__(name):
+    if name == "GateSolve":
+        return _autograd_function()
+    raise AttributeError(name)

@@ -94,19 +94,23 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
   dF = -dh * dv - 1.0;
 }
 
-// Safeguarded Newton (appendix B.2): bracket [lo, hi] with F(lo) > 0 > F(hi) grown from the
-// warm start, Newton steps while they stay inside, bisection otherwise.
+// Safeguarded Newton (appendix B.2): bracket [lo, hi] with F(lo) > 0 > F(hi), its first trial end
+// 1.5 Newton steps from the warm start (then doubling), Newton steps while they stay inside the
+// bracket, bisection otherwise; stops when the Newton correction or the bracket falls below
+// 1e-13 max(1, |S|) (normalised units, where F's rounding noise is ~1e-16 of its O(1) terms).
 __device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *steps) {
+  const double tol = 1e-13;
   if (c.alpha > 0.f && !(S0 > 0.0)) S0 = fmax(c.D, 1e-6);
   double F0, d0;
   F_eval(S0, L, c, G, F0, d0);
   *steps = 0;
   if (F0 == 0.0) return S0;
+  const double guess = (isfinite(F0) && isfinite(d0) && d0 < 0.0) ? -1.5 * F0 / d0 : 0.0;
   double lo, hi, Fs, dFs, S;
   if (F0 > 0.0) {
     lo = S0;
     double Flo = F0, dlo = d0;
-    double step = fmax(fabs(S0), 1e-6);
+    double step = guess > 0.0 ? guess : fmax(fabs(S0), 1e-6);
     hi = S0 + step;
     for (int i = 0; i < 1100; ++i) {
       double Fh, dh;
@@ -126,19 +130,19 @@ __device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *s
     hi = S0;
     double Fhi = F0, dhi = d0;
     if (c.alpha > 0.f) {
-      lo = S0;
+      lo = (guess < 0.0 && S0 + guess > 0.0) ? S0 + guess : 0.5 * S0;
       for (int i = 0; i < 1100; ++i) {
         double Fl, dl;
-        lo *= 0.5;
         F_eval(lo, L, c, G, Fl, dl);
         if (Fl == 0.0) return lo;
         if (Fl > 0.0) break;
         hi = lo;
         Fhi = Fl;
         dhi = dl;
+        lo *= 0.5;
       }
     } else {
-      double step = fmax(fabs(S0), 1e-6);
+      double step = guess < 0.0 ? -guess : fmax(fabs(S0), 1e-6);
       lo = S0 - step;
       for (int i = 0; i < 1100; ++i) {
         double Fl, dl;
@@ -160,7 +164,9 @@ __device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *s
     double Sn = 0.0;
     bool newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.0;
     if (newton) {
-      Sn = S - Fs / dFs;
+      const double step = Fs / dFs;
+      if (fabs(step) <= tol * fmax(fabs(S), 1.0)) return S - step;  // correction below tolerance
+      Sn = S - step;
       newton = (Sn > lo && Sn < hi);
     }
     if (!newton) Sn = 0.5 * (lo + hi);
@@ -169,11 +175,7 @@ __device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *s
     ++*steps;
     if (Fn == 0.0) return Sn;
     if (Fn > 0.0) lo = Sn; else hi = Sn;
-    // same criterion as the FP64 reference: 1e-13 relative above 1, absolute below (normalised
-    // units, where F's own rounding noise is ~1e-16 times its O(1) terms)
-    const double tol = 1e-13 * fmax(fabs(Sn), 1.0);
-    if (hi - lo <= tol) return Sn;
-    if (newton && fabs(Sn - S) <= tol) return Sn;
+    if (hi - lo <= tol * fmax(fabs(Sn), 1.0)) return Sn;
     S = Sn;
     Fs = Fn;
     dFs = dn;

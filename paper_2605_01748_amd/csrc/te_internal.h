@@ -62,15 +62,36 @@ struct State {
   float *x, *uneg;   // [P] path rates and non-negativity duals (FP32: the bulk of the state)
   double *udem, *S;  // [D] demand duals and last root of the sum equation
   double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
-  Ctrl *ctrl;        // [2]
+  Ctrl *ctrl;        // [3]
   double *partA;     // [2][nA][4]
   double *partB;     // [2][nB][4]
   int32_t nA, nB;
+  double *log_beta;  // nullable [log_cap]: (beta_k, alpha_k) actually used, written when recording
+  double *log_alpha;
+  int32_t log_cap;
+};
+
+// Adjoint state of the reverse pass (FP64), adjoints of one iteration's outputs.
+struct AdjState {
+  double *xb, *unb;  // [P]
+  double *udb;       // [D]
+  double *gb, *qb;   // [E]
+  double *ab;        // [P] scratch: adjoint of the consensus term a_r
+  double *Cb;        // [E] accumulated gradient w.r.t. capacities (normalised units)
+  double *Db;        // [D] accumulated gradient w.r.t. demands
+};
+
+// One stored forward state (the iteration state of State, without control data).
+struct FwdState {
+  float *x, *uneg;
+  double *udem, *S;
+  double2 *gq;
 };
 
 constexpr int kMaxLinkBlocks = 512;  // workgroups of the link kernel (partB rows), at most
 constexpr int kMaxLinksPerBlock = 1024;
-constexpr int kThreads = 256;        // threads per workgroup of the graph-engine kernels
+constexpr int kThreads = 256;        // threads per workgroup of the graph-engine demand kernels
+constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kBlockThreads = 1024;  // threads of the workgroup engine
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.

@@ -138,13 +138,20 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
     if (on) {
       const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
       n = i1 - i0;
-      for (int i = i0; i < i1; ++i) {
-        const double2 v = s.gq[p.plinks[i]];
-        sg += v.x;
-        sq += v.y;
-      }
       xr = s.x[r];
       ung = s.uneg[r];
+      for (int ib = i0; ib < i1; ib += 8) {  // link ids of up to 8 hops, then their (g, q) pairs
+        int e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (e[u] >= 0) {
+            const double2 v = s.gq[e[u]];
+            sg += v.x;
+            sq += v.y;
+          }
+      }
     }
     Dc = p.Dn[c];
     udc = s.udem[c];
@@ -191,6 +198,61 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
 }
 
+// Segmented sums over the CSC entries of the non-empty links k0..k1-1 owned by this workgroup:
+// acc[k - k0] += sum of vals[path] over the entries of link nzlink[k].  Each wavefront walks a
+// contiguous part in coalesced rows of 64 entries; runs of equal link in a row are reduced by a
+// segmented scan and their tail lane adds one partial into the LDS accumulator.
+template <class T>
+__device__ __forceinline__ void seg_rows_sum(const Prob &p, const T *vals, int k0, int k1, double *acc) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int j0 = p.nzptr[k0], j1 = p.nzptr[k1];
+  const int len = j1 - j0, per = (len + nw - 1) / nw;
+  const int ja = j0 + min(len, w * per), jb = j0 + min(len, (w + 1) * per);
+  if (ja >= jb) return;
+  int lo = k0, hi = k1 - 1;  // rank of the link holding entry ja
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p.nzptr[mid] <= ja) lo = mid; else hi = mid - 1;
+  }
+  int kbase = lo;
+  constexpr int U = 4;  // rows whose loads are issued together
+  for (int j = ja; j < jb; j += 64 * U) {
+    int32_t v[U];
+    double val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int jj = j + 64 * u + lane;
+      v[u] = jj < jb ? p.lpf[jj] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int jj = j + 64 * u + lane;
+      val[u] = jj < jb ? (double)vals[v[u] & 0x7fffffff] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int jj = j + 64 * u + lane;
+      const bool valid = jj < jb;
+      const bool head = valid && v[u] < 0 && jj != ja;
+      const uint64_t hm = __ballot(head);
+      const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int rank = kbase + __popcll(hm & le);
+      double x = val[u];
+      for (int d = 1; d < 64; d <<= 1) {
+        const double y = __shfl_up(x, d, 64);
+        const int ry = __shfl_up(rank, d, 64);
+        if (lane >= d && ry == rank) x += y;
+      }
+      const int rn = __shfl_down(rank, 1, 64);
+      const int vn = __shfl_down(valid ? 1 : 0, 1, 64);
+      const bool tail = valid && (lane == 63 || !vn || rn != rank);
+      if (tail) atomicAdd(&acc[rank - k0], x);
+      kbase += __popcll(hm);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Step a3 + a4: link loads by segmented FP64 sums over the CSC lists, capacity/consensus duals.
 // Workgroup b owns a contiguous range of non-empty links holding ~nnz/nB CSC entries; each
@@ -198,55 +260,27 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
 // link inside the row with a segmented scan and adds one partial per run into an LDS FP64
 // accumulator.  Also folds a slice of the demand kernel's partial sums into its row.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_link(Prob p, State s, const Params *prmp, int par) {
+__global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
   __shared__ double acc[kMaxLinksPerBlock];
   CtrlPrefetch cp;
   if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
   const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   __syncthreads();
-  const int j0 = p.nzptr[k0], j1 = p.nzptr[k1];
-  const int len = j1 - j0, per = (len + nw - 1) / nw;
-  const int ja = j0 + min(len, w * per), jb = j0 + min(len, (w + 1) * per);
-  if (ja < jb) {
-    // rank of the link holding entry ja
-    int lo = k0, hi = k1 - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (p.nzptr[mid] <= ja) lo = mid; else hi = mid - 1;
-    }
-    int kbase = lo;
-    for (int j = ja; j < jb; j += 64) {
-      const int jj = j + lane;
-      const bool valid = jj < jb;
-      const int32_t v = valid ? p.lpf[jj] : 0;
-      const bool head = valid && v < 0 && jj != ja;
-      const uint64_t hm = __ballot(head);
-      const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-      const int rank = kbase + __popcll(hm & le);
-      double val = valid ? (double)s.x[v & 0x7fffffff] : 0.0;
-      for (int d = 1; d < 64; d <<= 1) {
-        const double y = __shfl_up(val, d, 64);
-        const int ry = __shfl_up(rank, d, 64);
-        if (lane >= d && ry == rank) val += y;
-      }
-      const int rn = __shfl_down(rank, 1, 64);
-      const int vn = __shfl_down(valid ? 1 : 0, 1, 64);
-      const bool tail = valid && (lane == 63 || !vn || rn != rank);
-      if (tail) atomicAdd(&acc[rank - k0], val);
-      kbase += __popcll(hm);
-    }
-  }
+  seg_rows_sum(p, s.x, k0, k1, acc);
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     Ctrl wr = cs;
     wr.pending = cs.stop ? 0 : 1;
     s.ctrl[par] = wr;
+    if (s.log_beta && !cs.stop && cs.k < s.log_cap) {
+      s.log_beta[cs.k] = cs.beta;
+      s.log_alpha[cs.k] = cs.alpha;
+    }
   }
   if (cs.stop) return;
   const double inv_f = cs.inv_f;
@@ -746,6 +780,161 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
 }
 
 // ------------------------------------------------------------------------------------------
+// Reverse pass of one iteration (vector-Jacobian product, FP64), schedule and unit scale fixed.
+// fin: state at the start of iteration k, fout: state after it; rho: rescale of the scaled duals
+// at the start of iteration k.  Every [.]_+ differentiates on the branch taken; the root S* of the
+// sum equation through the implicit function theorem (dS* = -F_theta / F_S).
+// Inputs: a = adjoints of iteration k's outputs; outputs: adjoints of its inputs (in place).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, FwdState fout, AdjState a,
+                                                         double beta, float alpha, double rho) {
+  const int G = p.G;
+  const int t = threadIdx.x;
+  const int lane = t & (G - 1);
+  const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
+  if (c >= p.D) return;  // uniform in the lane group
+  const int r0 = p.dptr[c], np = p.dptr[c + 1] - r0;
+  const bool on = lane < np;
+  const int r = r0 + (on ? lane : 0);
+  int n = 1;
+  double sg = 0.0, sq = 0.0, lb = 0.0;
+  if (on) {
+    const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
+    n = i1 - i0;
+    for (int i = i0; i < i1; ++i) {
+      const int e = p.plinks[i];
+      const double2 v = fin.gq[e];
+      sg += v.x;
+      sq += v.y;
+      // link step adjoint: t_e = g~_e + (load_e - C_e)/(1+n_e), g' = [t]_+, q' = g~ - g'
+      const double tb = fout.gq[e].x > 0.0 ? (a.gb[e] - a.qb[e]) : 0.0;
+      lb += tb / (double)(1 + (p.lptr[e + 1] - p.lptr[e]));
+    }
+  }
+  const double Dc = (double)p.Dn[c];
+  const double udt = fin.udem[c] * rho;
+  const double unt = on ? (double)fin.uneg[r] * rho : 0.0;
+  const double a_r = on ? (double)n * (double)fin.x[r] - (sg * rho - sq) : 0.0;
+  double xb = on ? a.xb[r] + lb : 0.0;
+  // dual updates: u_dem' = [u~ + S - D]_+, u_neg' = [u~ - x']_+
+  const double v = fout.udem[c] > 0.0 ? a.udb[c] : 0.0;
+  double untb = (on && fout.uneg[r] > 0.0) ? a.unb[r] : 0.0;
+  xb -= untb;
+  xb += v;  // S_c = sum x'_r
+  double Dl = -v, udtb = v;
+  // rate update x' = xi(a - h(S*)) and the implicit root
+  const double Sst = fout.S[c];
+  Dem dm;
+  dm.D = Dc;
+  dm.u = udt;
+  dm.alpha = alpha;
+  dm.binv = 1.0 / beta;
+  const double tt = Sst - Dc + udt;
+  const double mh = tt > 0.0 ? 1.0 : 0.0;
+  const double pw = pow_neg_alpha(Sst, alpha);
+  const double h = fmax(tt, 0.0) - pw * dm.binv;
+  const double dh = mh + (alpha > 0.f ? (double)alpha * pw * dm.binv / Sst : 0.0);
+  const double b = a_r - h;
+  const bool hib = b >= (double)n * unt;
+  const double kap = on ? (hib ? 1.0 / n : 1.0 / (n + 1)) : 0.0;
+  const double xu = on ? (hib ? 0.0 : 1.0 / (n + 1)) : 0.0;
+  const double bb = xb * kap;
+  untb += xb * xu;
+  const double hb = -group_sum_d(bb, G);
+  const double skap = group_sum_d(kap, G);
+  double ab = bb;
+  const double Sstb = hb * dh;
+  Dl -= hb * mh;
+  udtb += hb * mh;
+  const double FS = -dh * skap - 1.0;
+  const double mu = -Sstb / FS;
+  ab += mu * kap;
+  untb += mu * xu;
+  Dl += mu * skap * mh;
+  udtb -= mu * skap * mh;
+  if (on) {
+    a.ab[r] = ab;
+    a.xb[r] = (double)n * ab;  // a_r = n_r x_r - ...
+    a.unb[r] = rho * untb;
+  }
+  if (lane == 0) {
+    a.udb[c] = rho * udtb;
+    a.Db[c] += Dl;
+  }
+}
+
+__global__ __launch_bounds__(kLinkThreads) void k_adj_link(Prob p, FwdState fout, AdjState a, double rho) {
+  __shared__ double acc[kMaxLinksPerBlock];
+  const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
+  for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
+  __syncthreads();
+  seg_rows_sum(p, a.ab, k0, k1, acc);
+  __syncthreads();
+  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+    const int e = p.nzlink[k];
+    const int ne = p.nzptr[k + 1] - p.nzptr[k];
+    const double sa = acc[k - k0];
+    const double tb = fout.gq[e].x > 0.0 ? (a.gb[e] - a.qb[e]) : 0.0;
+    a.Cb[e] -= tb / (double)(1 + ne);
+    const double gtb = tb + a.qb[e] - sa;  // g~ enters t, q' and (with minus) a_r
+    a.gb[e] = rho * gtb;
+    a.qb[e] = sa;
+  }
+}
+
+// seed: adjoint of x^(K) from the cotangent on S^(K) = sum_r x_r; zero everything else
+__global__ void k_adj_seed(Prob p, AdjState a, const float *dS) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      a.xb[r] = (double)dS[c];
+      a.unb[r] = 0.0;
+      a.ab[r] = 0.0;
+    }
+    a.udb[c] = 0.0;
+    a.Db[c] = 0.0;
+  }
+  for (int e = tid; e < p.E; e += nth) {
+    a.gb[e] = 0.0;
+    a.qb[e] = 0.0;
+    a.Cb[e] = 0.0;
+  }
+}
+
+// x^0_r = D_c / |P_c| (cold start): dD_c += sum_r xb_r / |P_c|
+__global__ void k_adj_x0(Prob p, AdjState a) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    const int r0 = p.dptr[c], r1 = p.dptr[c + 1];
+    double acc = 0.0;
+    for (int r = r0; r < r1; ++r) acc += a.xb[r];
+    a.Db[c] += acc / (double)(r1 - r0);
+  }
+}
+
+hipError_t launch_adj_seed(const Prob &p, const AdjState &a, const float *dS, hipStream_t st) {
+  int n = p.D > p.E ? p.D : p.E;
+  int blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_adj_seed, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, p, a, dS);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_iteration(const Prob &p, int nA, int nB, const FwdState &fin, const FwdState &fout,
+                                const AdjState &a, double beta, float alpha, double rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_demand, dim3(nA), dim3(kThreads), 0, st, p, fin, fout, a, beta, alpha, rho);
+  hipLaunchKernelGGL(k_adj_link, dim3(nB), dim3(kLinkThreads), 0, st, p, fout, a, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_x0(const Prob &p, const AdjState &a, hipStream_t st) {
+  int blocks = (p.D + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_adj_x0, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, p, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // host-side launchers
 // ------------------------------------------------------------------------------------------
 hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const float *x0, float inv_scale,
@@ -760,7 +949,7 @@ hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const f
 
 hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
   hipLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
-  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kThreads), 0, st, p, s, prm, par);
+  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
   return hipGetLastError();
 }
 
@@ -770,7 +959,7 @@ hipError_t launch_demand(const Prob &p, const State &s, const Params *prm, int p
 }
 
 hipError_t launch_link(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
-  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kThreads), 0, st, p, s, prm, par);
+  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
   return hipGetLastError();
 }
 

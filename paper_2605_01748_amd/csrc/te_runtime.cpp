@@ -27,6 +27,10 @@ hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *,
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
                               BatchOut *, size_t, hipStream_t);
 size_t block_lds_bytes(int E, int P, int D, int nnz);
+hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStream_t);
+hipError_t launch_adj_iteration(const Prob &, int, int, const FwdState &, const FwdState &, const AdjState &, double,
+                                float, double, hipStream_t);
+hipError_t launch_adj_x0(const Prob &, const AdjState &, hipStream_t);
 }  // namespace te
 
 using namespace te;
@@ -92,6 +96,16 @@ struct te_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing
   hipEvent_t pe[2] = {nullptr, nullptr};    // polling of the stop flag
   size_t lds_bytes = 0;
+  // recorded solve for te_grad
+  int32_t rec_K = 0, rec_ck = 16, rec_warm = 0;
+  double *d_log = nullptr;      // [2 * log_cap]: beta log then alpha log
+  int32_t log_cap = 0;
+  float *d_x0rec = nullptr;     // warm start of the recorded solve (caller units), if any
+  std::vector<FwdState> ckpt;   // checkpoints every rec_ck iterations
+  std::vector<Ctrl *> ckpt_ctrl;
+  std::vector<FwdState> seg;    // one segment of recomputed states
+  AdjState adj{};
+  int adj_ready = 0;
 };
 
 struct te_batch {
@@ -289,6 +303,33 @@ te_status build_chunk_graph(te_ctx *c, hipStream_t stream) {
   return TE_OK;
 }
 
+hipError_t alloc_fwd(FwdState &f, const te_ctx *c) {
+  hipError_t e = dalloc(&f.x, c->P);
+  if (e == hipSuccess) e = dalloc(&f.uneg, c->P);
+  if (e == hipSuccess) e = dalloc(&f.udem, c->D);
+  if (e == hipSuccess) e = dalloc(&f.S, c->D);
+  if (e == hipSuccess) e = dalloc(&f.gq, c->E);
+  return e;
+}
+
+void free_fwd(FwdState &f) {
+  void *b[] = {f.x, f.uneg, f.udem, f.S, f.gq};
+  for (void *p : b)
+    if (p) (void)hipFree(p);
+  f = FwdState{};
+}
+
+FwdState fwd_of(const State &s) { return FwdState{s.x, s.uneg, s.udem, s.S, s.gq}; }
+
+hipError_t copy_fwd(const FwdState &dst, const FwdState &src, const te_ctx *c, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(dst.x, src.x, sizeof(float) * c->P, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.uneg, src.uneg, sizeof(float) * c->P, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.udem, src.udem, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.S, src.S, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.gq, src.gq, sizeof(double2) * c->E, hipMemcpyDeviceToDevice, st);
+  return e;
+}
+
 void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms) {
   s->iters = c.k;
   s->flags = c.flags;
@@ -483,6 +524,10 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   hipStream_t stream = (hipStream_t)hip_stream;
   HIPCHK(hipSetDevice(c->device));
   int engine = o.engine;
+  if (o.record) {
+    if (o.fixed_iters <= 0) return fail(TE_ERR_INVALID, "record = 1 needs fixed_iters > 0");
+    engine = TE_ENGINE_GRAPH;
+  }
   if (engine == TE_ENGINE_AUTO) engine = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   if (engine == TE_ENGINE_BLOCK && c->lds_bytes > kMaxBlockLds)
     return fail(TE_ERR_INVALID, "instance needs %zu bytes of LDS, more than one workgroup has", c->lds_bytes);
@@ -498,7 +543,28 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     if (s != TE_OK) return s;
     HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, (float)(1.0 / c->scale), stream));
     int launched = 0;
-    if (o.fixed_iters > 0) {
+    if (o.record) {
+      // plain launches with the (beta, alpha) log; the gradient pass replays it
+      if (c->log_cap < o.fixed_iters) {
+        if (c->d_log) HIPCHK(hipFree(c->d_log));
+        c->d_log = nullptr;
+        HIPCHK(dalloc(&c->d_log, 2 * (size_t)o.fixed_iters));
+        c->log_cap = o.fixed_iters;
+      }
+      State sr = c->st;
+      sr.log_beta = c->d_log;
+      sr.log_alpha = c->d_log + c->log_cap;
+      sr.log_cap = c->log_cap;
+      for (launched = 0; launched < o.fixed_iters; ++launched)
+        HIPCHK(launch_iteration(c->prob, sr, c->d_params, launched & 1, stream));
+      c->rec_K = o.fixed_iters;
+      c->rec_ck = o.ckpt_every > 0 ? o.ckpt_every : 16;
+      c->rec_warm = x0_dev != nullptr;
+      if (x0_dev) {
+        if (!c->d_x0rec) HIPCHK(dalloc(&c->d_x0rec, c->P));
+        HIPCHK(hipMemcpyAsync(c->d_x0rec, x0_dev, sizeof(float) * c->P, hipMemcpyDeviceToDevice, stream));
+      }
+    } else if (o.fixed_iters > 0) {
       const int K = o.fixed_iters;
       while (launched + kChunk <= K) {
         HIPCHK(hipGraphLaunch(c->chunk, stream));
@@ -602,18 +668,104 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
 }
 
 te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_dev, double *dD_dev) {
-  (void)hip_stream;
-  (void)dS_dev;
-  (void)dC_dev;
-  (void)dD_dev;
-  if (!c) return fail(TE_ERR_INVALID, "null handle");
-  return fail(TE_ERR_STATE, "no recorded solve on this handle");
+  if (!c || !dS_dev || !dC_dev || !dD_dev) return fail(TE_ERR_INVALID, "null handle or buffer");
+  if (c->rec_K <= 0) return fail(TE_ERR_STATE, "no recorded solve on this handle (te_solve with record = 1)");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(c->device));
+  const int K = c->rec_K, ck = c->rec_ck;
+  const int nck = (K + ck - 1) / ck;
+  // the recorded schedule on the host (beta_k, alpha_k, rescale rho_k)
+  std::vector<double> lb(K), la(K);
+  HIPCHK(hipMemcpyAsync(lb.data(), c->d_log, sizeof(double) * K, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipMemcpyAsync(la.data(), c->d_log + c->log_cap, sizeof(double) * K, hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  // buffers (kept on the handle)
+  while ((int)c->ckpt.size() < nck) {
+    FwdState f{};
+    Ctrl *cc = nullptr;
+    if (alloc_fwd(f, c) != hipSuccess || dalloc(&cc, 1) != hipSuccess) {
+      free_fwd(f);
+      return fail(TE_ERR_OOM, "checkpoint allocation failed");
+    }
+    c->ckpt.push_back(f);
+    c->ckpt_ctrl.push_back(cc);
+  }
+  while ((int)c->seg.size() < ck + 1) {
+    FwdState f{};
+    if (alloc_fwd(f, c) != hipSuccess) {
+      free_fwd(f);
+      return fail(TE_ERR_OOM, "segment allocation failed");
+    }
+    c->seg.push_back(f);
+  }
+  if (!c->adj_ready) {
+    AdjState &a = c->adj;
+    bool ok = dalloc(&a.xb, c->P) == hipSuccess && dalloc(&a.unb, c->P) == hipSuccess &&
+              dalloc(&a.udb, c->D) == hipSuccess && dalloc(&a.gb, c->E) == hipSuccess &&
+              dalloc(&a.qb, c->E) == hipSuccess && dalloc(&a.ab, c->P) == hipSuccess;
+    if (!ok) return fail(TE_ERR_OOM, "adjoint allocation failed");
+    c->adj_ready = 1;
+  }
+  AdjState a = c->adj;
+  a.Cb = dC_dev;
+  a.Db = dD_dev;
+  // replay parameters: the recorded schedule, fixed iteration count
+  te_options o;
+  te_default_options(&o);
+  o.fixed_iters = K;
+  o.sched_beta = lb.data();
+  o.sched_alpha = la.data();
+  o.sched_len = K;
+  te_status s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
+  if (s != TE_OK) return s;
+  HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
+  const FwdState work = fwd_of(c->st);
+  // forward pass with checkpoints every ck iterations (state + the control record read by the next iteration)
+  HIPCHK(launch_init(c->prob, c->st, c->d_params, c->rec_warm ? c->d_x0rec : nullptr, (float)(1.0 / c->scale),
+                     stream));
+  for (int k = 0; k < K; ++k) {
+    if (k % ck == 0) {
+      HIPCHK(copy_fwd(c->ckpt[k / ck], work, c, stream));
+      HIPCHK(hipMemcpyAsync(c->ckpt_ctrl[k / ck], c->st.ctrl + ((k + 1) & 1), sizeof(Ctrl),
+                            hipMemcpyDeviceToDevice, stream));
+    }
+    HIPCHK(launch_iteration(c->prob, c->st, c->d_params, k & 1, stream));
+  }
+  // reverse, segment by segment
+  HIPCHK(launch_adj_seed(c->prob, a, dS_dev, stream));
+  for (int sgi = nck - 1; sgi >= 0; --sgi) {
+    const int k0 = sgi * ck, k1 = std::min(K, k0 + ck);
+    HIPCHK(copy_fwd(work, c->ckpt[sgi], c, stream));
+    HIPCHK(hipMemcpyAsync(c->st.ctrl + ((k0 + 1) & 1), c->ckpt_ctrl[sgi], sizeof(Ctrl), hipMemcpyDeviceToDevice,
+                          stream));
+    HIPCHK(copy_fwd(c->seg[0], work, c, stream));
+    for (int k = k0; k < k1; ++k) {
+      HIPCHK(launch_iteration(c->prob, c->st, c->d_params, k & 1, stream));
+      HIPCHK(copy_fwd(c->seg[k - k0 + 1], work, c, stream));
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+      const double rho = k > 0 ? lb[k - 1] / lb[k] : 1.0;
+      HIPCHK(launch_adj_iteration(c->prob, c->st.nA, c->st.nB, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
+                                  (float)la[k], rho, stream));
+    }
+  }
+  if (!c->rec_warm) HIPCHK(launch_adj_x0(c->prob, a, stream));
+  return TE_OK;
 }
 
 void te_destroy(te_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
+  for (auto &f : c->ckpt) free_fwd(f);
+  for (auto &f : c->seg) free_fwd(f);
+  for (Ctrl *p : c->ckpt_ctrl)
+    if (p) (void)hipFree(p);
+  {
+    void *ab[] = {c->adj.xb, c->adj.unb, c->adj.udb, c->adj.gb, c->adj.qb, c->adj.ab, c->d_log, c->d_x0rec};
+    for (void *p : ab)
+      if (p) (void)hipFree(p);
+  }
   void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.x, c->st.uneg, c->st.udem, c->st.S, c->st.gq, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
                   c->d_params, c->d_desc, c->d_bout, c->d_sched};

@@ -186,3 +186,47 @@ def test_invalid_options_rejected(te, c1):
 def _golden(name):
     import os
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+
+
+@pytest.mark.parametrize("which,K", [("tiny", 40), ("config1", 256)])
+def test_grad_matches_oracle_reverse_pass(te, c1, which, K):
+    """te_grad (adjoint kernels, checkpoints every 16 iterations) against the oracle's FP64 reverse
+    pass with the same replayed schedule: total throughput (cotangent 1) and sum of logs (1/S)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import torch
+    if which == "tiny":
+        from test_oracle_pins import _tiny_random
+        inst = _tiny_random(0)
+    else:
+        inst = c1
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    opts = te.Options(fixed_iters=K, project=False, record=True, engine=te.ENGINE_GRAPH, sched_beta=sb,
+                      sched_alpha=sa)
+    _, S, _ = prob.solve(opts)
+    S = S.cpu().numpy().astype(np.float64)
+    for wname in ("ones", "inv"):
+        w = np.ones(inst.n_demands) if wname == "ones" else 1.0 / np.maximum(np.abs(S), 1e-12)
+        dC, dD = prob.grad(torch.tensor(w, dtype=torch.float32))
+        dC = dC.cpu().numpy()
+        dD = dD.cpu().numpy()
+        _, oC, oD = O.grad(inst, sb, sa, w.astype(np.float32).astype(np.float64))
+        scale = max(np.abs(oC).max(), np.abs(oD).max())
+        eC = np.abs(dC - oC).max() / scale
+        eD = np.abs(dD - oD).max() / scale
+        print(f"grad {which} K={K} {wname}: max |err| / max |grad|: dC {eC:.2e} dD {eD:.2e}")
+        assert eC <= 1e-3 and eD <= 1e-3
+
+
+def test_gatesolve_autograd(te, c1, torch):
+    import torch as t
+    GateSolve = te.GateSolve
+    prob = te.Problem(c1)
+    C = t.tensor(c1.capacity, dtype=t.float64, requires_grad=True)
+    D = t.tensor(c1.demand, dtype=t.float64, requires_grad=True)
+    S = GateSolve.apply(prob, C, D, 64)
+    S.sum().backward()
+    assert C.grad.shape == C.shape and D.grad.shape == D.shape
+    assert t.isfinite(C.grad).all() and t.isfinite(D.grad).all()

@@ -139,6 +139,52 @@ def build_ksp() -> str:
     return out
 
 
+def k_shortest_paths_csr(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, k, chunk=8192):
+    """Vectorised variant for large pair sets: returns (paths per pair [npairs], path_ptr [P+1] int64,
+    path_links [nnz] int32), paths of a pair contiguous and in (cost, sequence) order."""
+    arc_src = np.ascontiguousarray(arc_src, dtype=np.int32)
+    arc_dst = np.ascontiguousarray(arc_dst, dtype=np.int32)
+    weight = np.ascontiguousarray(weight, dtype=np.float64)
+    m = arc_src.shape[0]
+    n = int(n_nodes)
+    out_arc = np.ascontiguousarray(np.lexsort((arc_dst, arc_src)), dtype=np.int32)
+    out_ptr = np.cumsum(np.concatenate([[0], np.bincount(arc_src, minlength=n)])).astype(np.int32)
+    in_arc = np.ascontiguousarray(np.lexsort((arc_src, arc_dst)), dtype=np.int32)
+    in_ptr = np.cumsum(np.concatenate([[0], np.bincount(arc_dst, minlength=n)])).astype(np.int32)
+    pair_src = np.ascontiguousarray(pair_src, dtype=np.int32)
+    pair_dst = np.ascontiguousarray(pair_dst, dtype=np.int32)
+    lib = _ksp()
+    hop_cap = max(n - 1, 1)
+    counts, hops_all, links_all = [], [], []
+    for s0 in range(0, pair_src.shape[0], chunk):
+        s1 = min(s0 + chunk, pair_src.shape[0])
+        q = s1 - s0
+        npaths = np.zeros(q, dtype=np.int32)
+        hops = np.zeros(q * k, dtype=np.int32)
+        arcs = np.zeros(q * k * hop_cap, dtype=np.int32)
+        kp = np.full(q, k, dtype=np.int32)
+        err = lib.ksp_batch(n, m, arc_src.ctypes.data, arc_dst.ctypes.data, weight.ctypes.data,
+                            out_ptr.ctypes.data, out_arc.ctypes.data, in_ptr.ctypes.data, in_arc.ctypes.data,
+                            q, np.ascontiguousarray(pair_src[s0:s1]).ctypes.data,
+                            np.ascontiguousarray(pair_dst[s0:s1]).ctypes.data, kp.ctypes.data, k,
+                            npaths.ctypes.data, hops.ctypes.data, arcs.ctypes.data)
+        if err:
+            raise RuntimeError("ksp_batch failed")
+        valid = (np.arange(k)[None, :] < npaths[:, None]).ravel()
+        h = hops[valid]
+        slot = np.nonzero(valid)[0]
+        # gather the hop lists of the valid slots
+        starts = slot * hop_cap
+        idx = np.repeat(starts - np.concatenate([[0], np.cumsum(h)[:-1]]), h) + np.arange(h.sum())
+        counts.append(npaths)
+        hops_all.append(h)
+        links_all.append(arcs[idx])
+    counts = np.concatenate(counts)
+    hops = np.concatenate(hops_all)
+    path_ptr = np.concatenate([[0], np.cumsum(hops)]).astype(np.int64)
+    return counts, path_ptr, np.concatenate(links_all).astype(np.int32)
+
+
 def k_shortest_paths(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, k_per, chunk=8192):
     """Returns, per pair, a list of paths, each a list of arc ids (first k in (cost, sequence) order)."""
     arc_src = np.ascontiguousarray(arc_src, dtype=np.int32)
@@ -325,6 +371,87 @@ def config2(seed: int = 0) -> Instance:
     paths = k_shortest_paths(n, src, dst, wgt, [p[0] for p in pairs], [p[1] for p in pairs], 8)
     return _assemble(f"config2/s{seed}", n, src, dst, cap, pairs, base, paths, 1.3,
                      dict(kind="config2", seed=seed, edges=len(edges)))
+
+
+def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_links: int = 80, gateways: int = 4,
+            backbone_links: int = 1000, k: int = 4, factor: float = 1.3, cache_dir: str | None = None) -> Instance:
+    """Hierarchical WAN: `regions` Waxman regions of `region_nodes` nodes (~`region_links` links each,
+    capacities {100, 400}) in their own unit sub-squares of a 10 x 5 layout, joined by a Waxman
+    backbone over `gateways` gateway nodes per region (~`backbone_links` links, capacities
+    {400, 1000}); all ordered pairs with gravity demands from 1 + Pareto(1.2) node weights; k
+    latency-shortest paths.  Scale: factor x the uniform-split bound lambda_unif (the largest lambda
+    for which lambda * D_gravity split evenly over each demand's paths fits every link), because the
+    max-concurrent-flow LP over ~4M path variables is not tractable here.  Cached as .npz when
+    cache_dir is given (the generation runs Yen's algorithm for ~1M pairs)."""
+    if cache_dir:
+        path = os.path.join(cache_dir, f"config3_s{seed}.npz")
+        if os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            return Instance(name=str(z["name"]), n_nodes=int(z["n_nodes"]), link_src=z["link_src"],
+                            link_dst=z["link_dst"], capacity=z["capacity"], demand_src=z["demand_src"],
+                            demand_dst=z["demand_dst"], demand=z["demand"], path_ptr=z["path_ptr"],
+                            path_links=z["path_links"], demand_path_ptr=z["demand_path_ptr"],
+                            meta=json.loads(str(z["meta"])))
+    rng = np.random.default_rng(np.random.SeedSequence([3, seed]))
+    n = regions * region_nodes
+    pos = np.zeros((n, 2))
+    edges, ecap = [], []
+    gw = []
+    cols = 10
+    for g in range(regions):
+        x0, y0 = (g % cols) * 1.0, (g // cols) * 1.0
+        p, e = waxman(region_nodes, region_links, rng, box=(x0, y0, x0 + 1.0, y0 + 1.0))
+        base = g * region_nodes
+        pos[base:base + region_nodes] = p
+        edges += [(u + base, v + base) for u, v in e]
+        ecap += list(rng.choice([100.0, 400.0], size=len(e)))
+        gw += list(base + rng.choice(region_nodes, size=gateways, replace=False))
+    gw = np.array(sorted(gw))
+    # backbone: Waxman over the gateway nodes at their actual positions, connected
+    for _ in range(1000):
+        iu, iv = np.triu_indices(len(gw), 1)
+        d = np.hypot(*(pos[gw[iu]] - pos[gw[iv]]).T)
+        base_p = np.exp(-d / (0.4 * d.max()))
+        beta_w = min(1.0, backbone_links / base_p.sum())
+        keep = rng.uniform(size=base_p.shape) < beta_w * base_p
+        bb = [(int(gw[a]), int(gw[b])) for a, b in zip(iu[keep], iv[keep])]
+        if _connected(n, edges + bb):
+            break
+    else:
+        raise RuntimeError("could not draw a connected backbone")
+    edges += bb
+    ecap += list(rng.choice([400.0, 1000.0], size=len(bb)))
+    src, dst, cap, wgt = arcs_from_edges(edges, ecap, pos)
+    w = 1.0 + rng.pareto(1.2, n)
+    ps, pt = np.nonzero(~np.eye(n, dtype=bool))
+    ps = ps.astype(np.int32)
+    pt = pt.astype(np.int32)
+    counts, path_ptr, path_links = k_shortest_paths_csr(n, src, dst, wgt, ps, pt, k)
+    keep = counts > 0
+    ps, pt = ps[keep], pt[keep]
+    base = gravity(w, ps, pt)
+    dptr = np.concatenate([[0], np.cumsum(counts[keep])]).astype(np.int32)
+    inst = Instance(name=f"config3/s{seed}", n_nodes=n, link_src=src, link_dst=dst, capacity=cap,
+                    demand_src=ps, demand_dst=pt, demand=base, path_ptr=path_ptr, path_links=path_links,
+                    demand_path_ptr=dptr, meta=dict(kind="config3", seed=seed, edges=len(edges),
+                                                    backbone_edges=len(bb)))
+    # uniform-split bound
+    m = np.diff(inst.demand_path_ptr)
+    path_of_inc = np.repeat(np.arange(inst.n_paths), np.diff(inst.path_ptr))
+    dem_of_path = np.repeat(np.arange(inst.n_demands), m)
+    per_path = base[dem_of_path] / m[dem_of_path]
+    load = np.bincount(inst.path_links, weights=per_path[path_of_inc], minlength=inst.n_links)
+    used = load > 0
+    lam = float(np.min(inst.capacity[used] / load[used]))
+    inst.demand = factor * lam * base
+    inst.meta.update(lambda_unif=lam, scale_factor=factor, dropped_pairs=int((~keep).sum()))
+    if cache_dir:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(os.path.join(cache_dir, f"config3_s{seed}.npz"), name=inst.name, n_nodes=inst.n_nodes,
+                 link_src=inst.link_src, link_dst=inst.link_dst, capacity=inst.capacity, demand_src=inst.demand_src,
+                 demand_dst=inst.demand_dst, demand=inst.demand, path_ptr=inst.path_ptr, path_links=inst.path_links,
+                 demand_path_ptr=inst.demand_path_ptr, meta=json.dumps(inst.meta))
+    return inst
 
 
 def config4_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
