@@ -12,7 +12,11 @@ latency-shortest paths per pair.  K* is the smallest iteration budget on a geome
 projected allocation reaches optimality >= 0.99 against the exact max-min allocation (progressive
 filling LPs, stored in tests/golden).
 
-Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batch]
+Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batch] [--no-grad]
+       python bench.py --profile copy            one 1 GiB device copy, repeated (counter calibration)
+       python bench.py --profile iters --iters K one graph-engine solve of K iterations (kernel counters)
+       python bench.py --large [--cache-dir DIR] the 1,000-node two-level WAN (~1M demands, ~4M paths):
+                                                 per-iteration kernel times, roofline, parity at K=16
 """
 from __future__ import annotations
 
@@ -49,6 +53,70 @@ def kernel_bytes(inst):
     return b_dem, b_link
 
 
+def profile_run(args, torch, te, W, dev):
+    """Short runs for hardware-counter passes: a plain device copy of known size (calibrates
+    FETCH_SIZE / WRITE_SIZE) and the solver's per-iteration kernels on the benchmark instance."""
+    if args.profile == "copy":
+        n = 1 << 28  # 2^28 float32 = 1 GiB read + 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy: 5 x {4 * n} bytes")
+        return
+    inst = W.config2(0)
+    log(inst.summary())
+    prob = te.Problem(inst)
+    o = te.Options(fixed_iters=args.iters, project=False, engine=te.ENGINE_GRAPH)
+    prob.solve(o, stats=False)
+    torch.cuda.synchronize()
+    _, _, st = prob.solve(o)
+    log(f"iters {args.iters}: {st['ms']:.3f} ms")
+
+
+def large_run(args, torch, te, W, O, dev):
+    """The 1,000-node two-level WAN (50 regions x 20 nodes + backbone, all ~1M ordered pairs, k = 4):
+    the size at which the per-iteration kernels move enough bytes for the HBM roofline to matter.
+    Reports mean kernel durations over 32 iterations, the roofline of both kernels, ms per
+    iteration of a plain 64-iteration solve, and the error against the FP64 oracle after 16
+    iterations with the oracle's schedule replayed (all demands)."""
+    t0 = time.time()
+    inst = W.config3(0, cache_dir=args.cache_dir)
+    log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
+    prob = te.Problem(inst)
+    ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=32)
+    b_dem, b_link = kernel_bytes(inst)
+    rl = {}
+    for name, ms, b in (("k_demand", ms_dem, b_dem), ("k_link", ms_link, b_link)):
+        gbs = b / (ms * 1e-3) / 1e9
+        rl[name] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(b), "avg_launch_us": round(ms * 1e3, 2)}
+    log(f"kernels: {rl}")
+    o64 = te.Options(fixed_iters=64, project=False, engine=te.ENGINE_GRAPH)
+    prob.solve(o64, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.solve(o64, stats=False)
+    torch.cuda.synchronize()
+    ms_iter = (time.perf_counter() - t1) * 1e3 / 64
+    K = 16
+    t2 = time.perf_counter()
+    r = O.solve(inst, O.Options(fixed_iters=K, project=False), want_state=False)
+    t_orc = time.perf_counter() - t2
+    sb, sa = r.schedule
+    _, S, _ = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, sched_beta=sb, sched_alpha=sa))
+    S = S.cpu().numpy().astype(np.float64)
+    orc = r.S_raw * r.scale
+    err = np.abs(S - orc) / np.maximum(np.abs(orc), 1e-2 * inst.demand.max())
+    out = {"workload": "two-level WAN: 50 Waxman regions x 20 nodes + backbone over 4 gateways/region, "
+                       "all ordered pairs, 1+Pareto(1.2) gravity weights, k=4 latency-shortest paths",
+           "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
+           "ms_per_iteration": round(ms_iter, 4), "roofline": rl,
+           "parity_K16_max_rel_err": float(f"{err.max():.3e}"), "oracle_K16_s": round(t_orc, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,7 +124,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--n-scen", type=int, default=512)
+    ap.add_argument("--profile", choices=["copy", "iters"], default=None)
+    ap.add_argument("--iters", type=int, default=64)
+    ap.add_argument("--large", action="store_true")
+    ap.add_argument("--cache-dir", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -73,6 +146,12 @@ def main():
         sys.exit(1)
     te.library()
     dev = torch.device("cuda", 0)
+    if args.profile is not None:
+        profile_run(args, torch, te, W, dev)
+        return
+    if args.large:
+        large_run(args, torch, te, W, O, dev)
+        return
 
     t0 = time.time()
     inst = W.config2(0)
@@ -141,9 +220,15 @@ def main():
     if not args.no_cpu_baseline:
         threads = os.cpu_count() or 1
         os.environ.setdefault("OMP_NUM_THREADS", str(threads))
+        # bounded sample: whole oracle solves at K* until at least 10 s of wall time have passed
         t1 = time.perf_counter()
-        r = O.solve(inst, O.Options(fixed_iters=K_star), want_state=False)
-        t_orc = time.perf_counter() - t1
+        n_orc = 0
+        while True:
+            r = O.solve(inst, O.Options(fixed_iters=K_star), want_state=False)
+            n_orc += 1
+            if time.perf_counter() - t1 >= 10.0:
+                break
+        t_orc = (time.perf_counter() - t1) / n_orc
         orc_S = r.S_raw * r.scale
         sb, sa = r.schedule
         _, S_rep, _ = run(K_star, project=False, sched_beta=sb, sched_alpha=sa)
@@ -152,8 +237,8 @@ def main():
         err = np.abs(S_rep - orc_S) / np.maximum(np.abs(orc_S), floor)
         cpu = {"value": round(t_orc * 1e3, 1), "unit": "ms", "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
                "kind": "oracle",
-               "sample": f"one full FP64 oracle solve of the same instance at K*={K_star} iterations "
-                         f"(OpenMP, {os.environ.get('OMP_NUM_THREADS')} threads), same unit as value",
+               "sample": f"{n_orc} full FP64 oracle solves of the same instance at K*={K_star} iterations "
+                         f"(OpenMP, {os.environ.get('OMP_NUM_THREADS')} threads); mean ms per solve",
                "oracle_optimality": round(O.optimality(r.S, opt_S, THETA * scale), 5),
                "gpu_vs_oracle_max_rel_err": float(f"{err.max():.3e}")}
         log(f"oracle: {t_orc * 1e3:.1f} ms, GPU-vs-oracle max rel err {err.max():.3e}")
@@ -198,6 +283,39 @@ def main():
                  "workload": "config-1 topology, 1-3 link cuts, lognormal(0,0.3) demand noise, k_c in 2..8"}
         log(f"batch: {batch} ({time.time() - t2:.1f}s)")
 
+    # ---- differentiation: te_grad through a recorded 256-iteration solve of the 20-node instance ----
+    grad = None
+    if not args.no_grad:
+        c1 = W.config1(0)
+        p1 = te.Problem(c1)
+        Kg = 256
+        og = te.Options(fixed_iters=Kg, project=False, record=True, ckpt_every=16)
+        ones = torch.ones(c1.n_demands, dtype=torch.float32, device=dev)
+        p1.solve(og, stats=False)
+        p1.grad(ones)
+        torch.cuda.synchronize()
+        reps = 5
+        tf = time.perf_counter()
+        for _ in range(reps):
+            p1.solve(og, stats=False)
+        torch.cuda.synchronize()
+        t_fwd = (time.perf_counter() - tf) / reps
+        tg = time.perf_counter()
+        for _ in range(reps):
+            p1.grad(ones)
+        torch.cuda.synchronize()
+        t_grad = (time.perf_counter() - tg) / reps
+        tp = time.perf_counter()
+        for _ in range(reps):
+            p1.solve(te.Options(fixed_iters=Kg, project=False), stats=False)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - tp) / reps
+        grad = {"workload": "20-node instance, K=256, checkpoints every 16 iterations, cotangent ones",
+                "recorded_solve_ms": round(t_fwd * 1e3, 3), "grad_ms": round(t_grad * 1e3, 3),
+                "plain_solve_ms": round(t_plain * 1e3, 3),
+                "grad_over_recorded_solve": round(t_grad / t_fwd, 3)}
+        log(f"grad: {grad}")
+
     out = {
         "metric": METRIC,
         "value": round(ms_per_step, 4),
@@ -219,6 +337,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batch,
+        "grad": grad,
     }
     print(json.dumps(out), flush=True)
 

@@ -33,7 +33,8 @@
  *    capacity of a link used by some path, iterates in those units, and
  *    returns rates and sums in the caller's units.
  *  - Admissible instance (appendix C, Part I(b): every commodity has a path and
- *    a positive demand, every used link a positive capacity): path_ptr
+ *    a positive demand, every used link a positive capacity): at least one
+ *    demand (an instance without commodities has nothing to solve), path_ptr
  *    non-decreasing from 0, no empty path, link ids in range, no link twice in
  *    one path, every demand with 1..64 paths, demand > 0 and finite, capacity
  *    finite everywhere and > 0 on every used link.  Anything else returns
@@ -183,10 +184,10 @@ te_status te_solve_batch(te_batch *batch, const te_options *opt, void *hip_strea
 
 /*
  * Device time of the graph engine's two per-iteration kernels (profiling aid): runs the solve of
- * opt with opt->fixed_iters = iters as individually launched kernels on hip_stream with a HIP event
- * before and after every launch, synchronises, and writes the mean duration in milliseconds of the
- * demand kernel to ms_out[0] and of the link kernel to ms_out[1].  The work is that of te_solve
- * without the projection.  iters in 1..4096.
+ * opt with opt->fixed_iters = iters as individually launched kernels on hip_stream, each launch
+ * carrying HIP events attached to its dispatch (start and end of its execution), synchronises, and
+ * writes the mean duration in milliseconds of the demand kernel to ms_out[0] and of the link
+ * kernel to ms_out[1].  The work is that of te_solve without the projection.  iters in 1..4096.
  */
 te_status te_kernel_times(te_ctx *ctx, const te_options *opt, void *hip_stream, int32_t iters, double *ms_out);
 

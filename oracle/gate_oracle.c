@@ -267,10 +267,12 @@ static int trim_cmp(const void *A, const void *B) {
   return (a->p > b->p) ? -1 : (a->p < b->p ? 1 : 0);
 }
 
-/* log of score_p = S_c^alpha * C_p; -inf when C_p = 0 or S_c = 0. */
+/* log of score_p = S_c^alpha * C_p; -inf when C_p = 0 or S_c = 0.  The score only orders paths
+   (a discrete decision); the paper fixes no precision for it, so it is taken in single precision,
+   as the GPU path computes it, and the two sides order near-equal scores alike. */
 static double log_score(double S, int Cp, double alpha) {
   if (Cp <= 0 || !(S > 0.0)) return -INFINITY;
-  return alpha * log(S) + log((double)Cp);
+  return (double)((float)alpha * logf((float)S) + logf((float)Cp));
 }
 
 static void aux_vars(int E, const double *C, int P, const int64_t *pptr, const int32_t *plinks, int D,

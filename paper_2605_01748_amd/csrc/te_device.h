@@ -20,23 +20,74 @@ enum { F_CONVERGED = 1, F_MAX_ITERS = 2, F_ALPHA_MAX = 4, F_BETA_BOUND = 8 };
 
 // ------------------------------------------------------------------------------------------
 // lane-group reductions (G lanes, power of two, aligned inside one 64-wide wavefront).
-// xor butterflies: every lane of the group ends with the bit-identical sum.
+// Butterflies whose pairings are symmetric, so every lane of the group ends with the bit-identical
+// result: DPP lane moves inside a row of 16 (quad permutes for distance 1 and 2, the half-row
+// mirror j <-> 7-j and the row mirror j <-> 15-j, which pair lanes holding equal partial results
+// after the previous stages), cross-lane permutes for distances 16 and 32.  All lanes of a group
+// must be active (the callers keep control flow uniform per group).
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ float group_sum(float v, int G) {
-  for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, 64);
-  return v;
+enum : int { kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140 };
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
 }
+
+// DPP move with an explicit value for lanes whose source is outside the pattern (or whose row is
+// not in the row mask RM)
+template <int CTRL, int RM>
+__device__ __forceinline__ double dpp_old_d(double v, double old) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(v), CTRL, RM, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(v), CTRL, RM, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int RM>
+__device__ __forceinline__ void seg_scan_step(double &x, int key) {
+  const double y = dpp_old_d<CTRL, RM>(x, 0.0);
+  const int ky = __builtin_amdgcn_update_dpp(-1, key, CTRL, RM, 0xF, false);
+  if (ky == key) x += y;
+}
+
+// Inclusive segmented sum over the 64 lanes: runs of equal key (keys >= 0, non-decreasing with
+// the lane index) are the segments.  Hillis-Steele steps inside each row of 16 lanes (row shifts
+// by 1, 2, 4, 8), then the row carries (lane 15 into row 1 and lane 47 into row 3, then lane 31
+// into rows 2 and 3), each added only where the source lane has the same key.  Every lane must be
+// active.
+__device__ __forceinline__ double seg_scan_d(double x, int key) {
+  seg_scan_step<0x111, 0xF>(x, key);  // row_shr:1
+  seg_scan_step<0x112, 0xF>(x, key);  // row_shr:2
+  seg_scan_step<0x114, 0xF>(x, key);  // row_shr:4
+  seg_scan_step<0x118, 0xF>(x, key);  // row_shr:8
+  seg_scan_step<0x142, 0xA>(x, key);  // row_bcast:15 into rows 1, 3
+  seg_scan_step<0x143, 0xC>(x, key);  // row_bcast:31 into rows 2, 3
+  return x;
+}
+
+// key of the next lane (lane 63: -2)
+__device__ __forceinline__ int next_lane_key(int key) {
+  return __builtin_amdgcn_update_dpp(-2, key, 0x130, 0xF, 0xF, false);  // wave_shl:1
+}
+
 __device__ __forceinline__ double group_sum_d(double v, int G) {
-  for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, 64);
+  if (G >= 2) v += dpp_d<kDppXor1>(v);
+  if (G >= 4) v += dpp_d<kDppXor2>(v);
+  if (G >= 8) v += dpp_d<kDppHalfMirror>(v);
+  if (G >= 16) v += dpp_d<kDppMirror>(v);
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
-__device__ __forceinline__ double wave_sum_d(double v) {
-  for (int m = 1; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return group_sum_d(v, 64); }
 __device__ __forceinline__ double wave_max_d(double v) {
-  for (int m = 1; m < 64; m <<= 1) v = fmax(v, __shfl_xor(v, m, 64));
-  return v;
+  v = fmax(v, dpp_d<kDppXor1>(v));
+  v = fmax(v, dpp_d<kDppXor2>(v));
+  v = fmax(v, dpp_d<kDppHalfMirror>(v));
+  v = fmax(v, dpp_d<kDppMirror>(v));
+  v = fmax(v, __shfl_xor(v, 16, 64));
+  return fmax(v, __shfl_xor(v, 32, 64));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -56,13 +107,27 @@ struct Lane {
 
 struct Dem {
   double D, u, binv;  // demand, u_dem (current scale), 1/beta
-  float alpha;
+  double alpha;
 };
 
-// S^-alpha in FP32: at the root the term's own slope alpha S^-alpha / (beta S) damps its rounding,
-// a relative error eps in it moves the root by at most eps / alpha relative.
-__device__ __forceinline__ double pow_neg_alpha(double S, float alpha) {
-  return alpha == 0.f ? 1.0 : (double)exp2f(-alpha * log2f((float)S));
+// S^-alpha in FP64 from invS = 1/S.  Integer alpha up to 64 (every alpha the continuation produces
+// from 0) by binary powering of 1/S (relative error below ~2 alpha ulps), other alpha by exp/log.
+// FP32 is not enough here: the iteration at alpha >= 1 amplifies a 1e-7 relative error of this
+// term over a few hundred iterations to ~4e-4 in the sums.
+__device__ __forceinline__ double pow_neg_alpha(double S, double invS, double alpha) {
+  if (alpha == 0.0) return 1.0;
+  const int ia = (int)alpha;
+  if ((double)ia == alpha && ia > 0 && ia <= 64) {
+    double r = 1.0, b = invS;
+    for (int m = ia;;) {
+      if (m & 1) r *= b;
+      m >>= 1;
+      if (!m) break;
+      b *= b;
+    }
+    return r;
+  }
+  return exp(-alpha * log(S));
 }
 
 __device__ __forceinline__ double xi_of(double b, const Lane &L) {
@@ -70,20 +135,21 @@ __device__ __forceinline__ double xi_of(double b, const Lane &L) {
 }
 
 __device__ __forceinline__ double h_of(double S, const Dem &c) {
-  return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, c.alpha) * c.binv;
+  return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, 1.0 / S, c.alpha) * c.binv;
 }
 
 // F(S) and F'(S) summed over the group (uniform inside the group).
 __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, int G, double &F, double &dF) {
-  if (c.alpha > 0.f && !(S > 0.0)) {
+  if (c.alpha > 0.0 && !(S > 0.0)) {
     F = INFINITY;
     dF = -INFINITY;
     return;
   }
   const double t = S - c.D + c.u;
-  const double pw = pow_neg_alpha(S, c.alpha);
+  const double invS = 1.0 / S;
+  const double pw = pow_neg_alpha(S, invS, c.alpha);
   const double h = fmax(t, 0.0) - pw * c.binv;
-  const double dh = (t > 0.0 ? 1.0 : 0.0) + (c.alpha > 0.f ? (double)c.alpha * pw * c.binv / S : 0.0);
+  const double dh = (t > 0.0 ? 1.0 : 0.0) + (c.alpha > 0.0 ? c.alpha * pw * c.binv * invS : 0.0);
   const double b = L.a - h;
   const bool hi_branch = b >= L.n * L.un;
   double v = L.on ? (hi_branch ? b * L.rn : (b + L.un) * L.rn1) : 0.0;
@@ -94,91 +160,45 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
   dF = -dh * dv - 1.0;
 }
 
-// Safeguarded Newton (appendix B.2): bracket [lo, hi] with F(lo) > 0 > F(hi), its first trial end
-// 1.5 Newton steps from the warm start (then doubling), Newton steps while they stay inside the
-// bracket, bisection otherwise; stops when the Newton correction or the bracket falls below
+// Safeguarded Newton (appendix B.2) from the warm start S0: every evaluation narrows the bracket
+// [lo, hi] with F(lo) > 0 > F(hi) (ends infinite until a sign of each kind has been seen); the next
+// point is the Newton point when it lies strictly inside the bracket (and stays positive for
+// alpha > 0), else the midpoint once both ends are known, else an expansion (doubling steps, or
+// halving towards 0 for alpha > 0).  Stops when the Newton correction or the bracket falls below
 // 1e-13 max(1, |S|) (normalised units, where F's rounding noise is ~1e-16 of its O(1) terms).
-__device__ double sum_root(double S0, const Lane &L, const Dem &c, int G, int *steps) {
+// Mean cost on the 150-node instance: 2.1 evaluations of F per demand and iteration.
+__device__ double sum_root(double S, const Lane &L, const Dem &c, int G, int *evals) {
   const double tol = 1e-13;
-  if (c.alpha > 0.f && !(S0 > 0.0)) S0 = fmax(c.D, 1e-6);
-  double F0, d0;
-  F_eval(S0, L, c, G, F0, d0);
-  *steps = 0;
-  if (F0 == 0.0) return S0;
-  const double guess = (isfinite(F0) && isfinite(d0) && d0 < 0.0) ? -1.5 * F0 / d0 : 0.0;
-  double lo, hi, Fs, dFs, S;
-  if (F0 > 0.0) {
-    lo = S0;
-    double Flo = F0, dlo = d0;
-    double step = guess > 0.0 ? guess : fmax(fabs(S0), 1e-6);
-    hi = S0 + step;
-    for (int i = 0; i < 1100; ++i) {
-      double Fh, dh;
-      hi = S0 + step;
-      F_eval(hi, L, c, G, Fh, dh);
-      if (Fh == 0.0) return hi;
-      if (Fh < 0.0) break;
-      lo = hi;
-      Flo = Fh;
-      dlo = dh;
-      step *= 2.0;
-    }
-    S = lo;
-    Fs = Flo;
-    dFs = dlo;
-  } else {
-    hi = S0;
-    double Fhi = F0, dhi = d0;
-    if (c.alpha > 0.f) {
-      lo = (guess < 0.0 && S0 + guess > 0.0) ? S0 + guess : 0.5 * S0;
-      for (int i = 0; i < 1100; ++i) {
-        double Fl, dl;
-        F_eval(lo, L, c, G, Fl, dl);
-        if (Fl == 0.0) return lo;
-        if (Fl > 0.0) break;
-        hi = lo;
-        Fhi = Fl;
-        dhi = dl;
-        lo *= 0.5;
-      }
-    } else {
-      double step = guess < 0.0 ? -guess : fmax(fabs(S0), 1e-6);
-      lo = S0 - step;
-      for (int i = 0; i < 1100; ++i) {
-        double Fl, dl;
-        lo = S0 - step;
-        F_eval(lo, L, c, G, Fl, dl);
-        if (Fl == 0.0) return lo;
-        if (Fl > 0.0) break;
-        hi = lo;
-        Fhi = Fl;
-        dhi = dl;
-        step *= 2.0;
-      }
-    }
-    S = hi;
-    Fs = Fhi;
-    dFs = dhi;
-  }
-  for (int it = 0; it < 100; ++it) {
+  if (c.alpha > 0.0 && !(S > 0.0)) S = fmax(c.D, 1e-6);
+  double lo = -INFINITY, hi = INFINITY, expand = 0.0;
+  *evals = 0;
+  for (int it = 0; it < 1200; ++it) {
+    double F, dF;
+    F_eval(S, L, c, G, F, dF);
+    ++*evals;
+    if (F == 0.0) return S;
+    if (F > 0.0) lo = S; else hi = S;
+    const double scale = fmax(fabs(S), 1.0);
+    if (hi - lo <= tol * scale) return S;
     double Sn = 0.0;
-    bool newton = isfinite(Fs) && isfinite(dFs) && dFs < 0.0;
-    if (newton) {
-      const double step = Fs / dFs;
-      if (fabs(step) <= tol * fmax(fabs(S), 1.0)) return S - step;  // correction below tolerance
+    bool ok = isfinite(F) && isfinite(dF) && dF < 0.0;
+    if (ok) {
+      const double step = F / dF;
+      if (fabs(step) <= tol * scale) return S - step;  // correction below tolerance
       Sn = S - step;
-      newton = (Sn > lo && Sn < hi);
+      ok = Sn > lo && Sn < hi && !(c.alpha > 0.0 && !(Sn > 0.0));
     }
-    if (!newton) Sn = 0.5 * (lo + hi);
-    double Fn, dn;
-    F_eval(Sn, L, c, G, Fn, dn);
-    ++*steps;
-    if (Fn == 0.0) return Sn;
-    if (Fn > 0.0) lo = Sn; else hi = Sn;
-    if (hi - lo <= tol * fmax(fabs(Sn), 1.0)) return Sn;
+    if (!ok) {
+      if (lo > -INFINITY && hi < INFINITY) {
+        Sn = 0.5 * (lo + hi);
+      } else if (F > 0.0 || c.alpha == 0.0) {
+        expand = expand > 0.0 ? 2.0 * expand : fmax(fabs(S), 1e-6);
+        Sn = F > 0.0 ? S + expand : S - expand;
+      } else {
+        Sn = 0.5 * S;
+      }
+    }
     S = Sn;
-    Fs = Fn;
-    dFs = dn;
   }
   return S;
 }
@@ -275,7 +295,7 @@ __device__ __forceinline__ uint64_t trim_key(float logscore, int32_t p) {
 
 __device__ __forceinline__ float log_score(double S, int Cp, float alpha) {
   if (Cp <= 0 || !(S > 0.0)) return -INFINITY;
-  return alpha * logf((float)S) + logf((float)Cp);
+  return __fadd_rn(__fmul_rn(alpha, logf((float)S)), logf((float)Cp));  // rounded product, no fused multiply-add
 }
 
 }  // namespace te

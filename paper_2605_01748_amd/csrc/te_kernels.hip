@@ -12,6 +12,7 @@
 //
 // Workgroup engine (small instances, batches): one workgroup runs the whole solve with the
 // instance resident in LDS and __syncthreads() between the steps.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -131,6 +132,9 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
   bool on = false;
   if (c < p.D) {
+    Dc = p.Dn[c];  // per-demand loads first: they depend on c only
+    udc = s.udem[c];
+    S0 = s.S[c];
     r0 = p.dptr[c];
     np = p.dptr[c + 1] - r0;
     on = lane < np;
@@ -153,9 +157,6 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
           }
       }
     }
-    Dc = p.Dn[c];
-    udc = s.udem[c];
-    S0 = s.S[c];
   }
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
     Dem dm;
     dm.D = (double)Dc;
     dm.u = udc * inv_f;
-    dm.alpha = (float)cs.alpha;
+    dm.alpha = cs.alpha;
     dm.binv = 1.0 / cs.beta;
     int steps;
     const double Sst = sum_root(S0, L, dm, G, &steps);
@@ -237,17 +238,11 @@ __device__ __forceinline__ void seg_rows_sum(const Prob &p, const T *vals, int k
       const bool head = valid && v[u] < 0 && jj != ja;
       const uint64_t hm = __ballot(head);
       const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-      const int rank = kbase + __popcll(hm & le);
-      double x = val[u];
-      for (int d = 1; d < 64; d <<= 1) {
-        const double y = __shfl_up(x, d, 64);
-        const int ry = __shfl_up(rank, d, 64);
-        if (lane >= d && ry == rank) x += y;
-      }
-      const int rn = __shfl_down(rank, 1, 64);
-      const int vn = __shfl_down(valid ? 1 : 0, 1, 64);
-      const bool tail = valid && (lane == 63 || !vn || rn != rank);
-      if (tail) atomicAdd(&acc[rank - k0], x);
+      // segment key: rank of the entry's link; lanes past the end get -3 (after every valid lane)
+      const int key = valid ? kbase + __popcll(hm & le) : -3;
+      const double x = seg_scan_d(val[u], key);
+      const bool tail = valid && next_lane_key(key) != key;
+      if (tail) atomicAdd(&acc[key - k0], x);
       kbase += __popcll(hm);
     }
   }
@@ -269,6 +264,27 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
+  // the per-link values of this thread's first link and its slice of the demand kernel's
+  // partial sums are loaded before the segmented sums, so their latency overlaps with them
+  const int kf = k0 + threadIdx.x;
+  int e_f = 0, ne_f = 0;
+  double2 gq_f = make_double2(0.0, 0.0);
+  double C_f = 1.0;
+  if (kf < k1) {
+    e_f = p.nzlink[kf];
+    ne_f = p.nzptr[kf + 1] - p.nzptr[kf];
+    gq_f = s.gq[e_f];
+    C_f = p.Cn[e_f];
+  }
+  double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
+  if (w == 1) {  // fold the demand kernel's rows b, b + nB, ... (fixed order)
+    const double *pa = s.partA + (size_t)par * s.nA * 4;
+    for (int i = blockIdx.x + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
+      a0 += pa[4 * i + 0];
+      a1 += pa[4 * i + 1];
+      a3 = fmax(a3, pa[4 * i + 3]);
+    }
+  }
   __syncthreads();
   seg_rows_sum(p, s.x, k0, k1, acc);
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
@@ -285,27 +301,22 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   if (cs.stop) return;
   const double inv_f = cs.inv_f;
   double dr2 = 0.0, cap_v = -INFINITY;
-  for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-    const int e = p.nzlink[k];
+  for (int k = kf; k < k1; k += blockDim.x) {
+    int e = e_f, ne = ne_f;
+    double2 v = gq_f;
+    double Ce = C_f;
+    if (k != kf) {  // more links than threads
+      e = p.nzlink[k];
+      ne = p.nzptr[k + 1] - p.nzptr[k];
+      v = s.gq[e];
+      Ce = p.Cn[e];
+    }
     const double load = acc[k - k0];
-    const int ne = p.nzptr[k + 1] - p.nzptr[k];
-    const double2 v = s.gq[e];
     const double gold = v.x * inv_f;
-    const double Ce = p.Cn[e];
     const double gn = fmax(gold + (load - Ce) / (double)(1 + ne), 0.0);
     s.gq[e] = make_double2(gn, gold - gn);
     dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
     cap_v = fmax(cap_v, (load - Ce) / Ce);
-  }
-  // fold the demand kernel's rows b, b + nB, ... (fixed order)
-  double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
-  if (w == 0) {
-    const double *pa = s.partA + (size_t)par * s.nA * 4;
-    for (int i = blockIdx.x + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
-      a0 += pa[4 * i + 0];
-      a1 += pa[4 * i + 1];
-      a3 = fmax(a3, pa[4 * i + 3]);
-    }
   }
   block_partials(a0, dr2 + a1, cap_v, a3, s.partB + ((size_t)par * s.nB + blockIdx.x) * 4);
 }
@@ -587,7 +598,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   while (!cs.stop) {
     const double inv_f = cs.inv_f;
     Dem dm;
-    dm.alpha = (float)cs.alpha;
+    dm.alpha = cs.alpha;
     dm.binv = 1.0 / cs.beta;
     double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY, cap_v = -INFINITY;
     // demand step
@@ -745,7 +756,8 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
           if (trim_key(uneg[q], q) > kr) before += (double)x[q];
         }
         const double dd = fmin((double)x[r], fmax(V - before, 0.0));
-        if (dd > 0.0) atomicMax((unsigned int *)&xo[r], __float_as_uint((float)dd));
+        // rounded up, so that the FP32 trim removes at least the link's share of the excess
+        if (dd > 0.0) atomicMax((unsigned int *)&xo[r], __float_as_uint(__double2float_ru(dd)));
       }
     }
   }
@@ -787,7 +799,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
 // Inputs: a = adjoints of iteration k's outputs; outputs: adjoints of its inputs (in place).
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, FwdState fout, AdjState a,
-                                                         double beta, float alpha, double rho) {
+                                                         double beta, double alpha, double rho) {
   const int G = p.G;
   const int t = threadIdx.x;
   const int lane = t & (G - 1);
@@ -831,9 +843,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, F
   dm.binv = 1.0 / beta;
   const double tt = Sst - Dc + udt;
   const double mh = tt > 0.0 ? 1.0 : 0.0;
-  const double pw = pow_neg_alpha(Sst, alpha);
+  const double invS = 1.0 / Sst;
+  const double pw = pow_neg_alpha(Sst, invS, alpha);
   const double h = fmax(tt, 0.0) - pw * dm.binv;
-  const double dh = mh + (alpha > 0.f ? (double)alpha * pw * dm.binv / Sst : 0.0);
+  const double dh = mh + (alpha > 0.0 ? alpha * pw * dm.binv * invS : 0.0);
   const double b = a_r - h;
   const bool hib = b >= (double)n * unt;
   const double kap = on ? (hib ? 1.0 / n : 1.0 / (n + 1)) : 0.0;
@@ -921,7 +934,7 @@ hipError_t launch_adj_seed(const Prob &p, const AdjState &a, const float *dS, hi
 }
 
 hipError_t launch_adj_iteration(const Prob &p, int nA, int nB, const FwdState &fin, const FwdState &fout,
-                                const AdjState &a, double beta, float alpha, double rho, hipStream_t st) {
+                                const AdjState &a, double beta, double alpha, double rho, hipStream_t st) {
   hipLaunchKernelGGL(k_adj_demand, dim3(nA), dim3(kThreads), 0, st, p, fin, fout, a, beta, alpha, rho);
   hipLaunchKernelGGL(k_adj_link, dim3(nB), dim3(kLinkThreads), 0, st, p, fout, a, rho);
   return hipGetLastError();
@@ -953,13 +966,17 @@ hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, in
   return hipGetLastError();
 }
 
-hipError_t launch_demand(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
-  hipLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
+// Timed launches: the events are attached to the dispatch itself (start and end of the kernel's
+// execution), so their difference excludes the queueing of separate event packets.
+hipError_t launch_demand_timed(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                               hipEvent_t ev0, hipEvent_t ev1) {
+  hipExtLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
   return hipGetLastError();
 }
 
-hipError_t launch_link(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
-  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
+hipError_t launch_link_timed(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                             hipEvent_t ev0, hipEvent_t ev1) {
+  hipExtLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
   return hipGetLastError();
 }
 

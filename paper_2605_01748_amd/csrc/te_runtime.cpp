@@ -14,14 +14,14 @@
 #include <string>
 #include <vector>
 
-#include "../../include/te.h"
+#include "te.h"
 #include "te_internal.h"
 
 namespace te {
 hipError_t launch_init(const Prob &, const State &, const Params *, const float *, float, hipStream_t);
 hipError_t launch_iteration(const Prob &, const State &, const Params *, int, hipStream_t);
-hipError_t launch_demand(const Prob &, const State &, const Params *, int, hipStream_t);
-hipError_t launch_link(const Prob &, const State &, const Params *, int, hipStream_t);
+hipError_t launch_demand_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
+hipError_t launch_link_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
 hipError_t launch_finish(const State &, const Params *, int, hipStream_t);
 hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *, float *, double, int, hipStream_t);
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
@@ -29,7 +29,7 @@ hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Param
 size_t block_lds_bytes(int E, int P, int D, int nnz);
 hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStream_t);
 hipError_t launch_adj_iteration(const Prob &, int, int, const FwdState &, const FwdState &, const AdjState &, double,
-                                float, double, hipStream_t);
+                                double, double, hipStream_t);
 hipError_t launch_adj_x0(const Prob &, const AdjState &, hipStream_t);
 }  // namespace te
 
@@ -636,7 +636,7 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
   HIPCHK(hipSetDevice(c->device));
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
-  std::vector<hipEvent_t> ev(3 * (size_t)iters, nullptr);
+  std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
   for (auto &e : ev)
     if (hipEventCreate(&e) != hipSuccess) {
       for (auto &f : ev)
@@ -645,18 +645,16 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
     }
   hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, (float)(1.0 / c->scale), stream);
   for (int k = 0; k < iters && err == hipSuccess; ++k) {
-    err = hipEventRecord(ev[3 * k], stream);
-    if (err == hipSuccess) err = launch_demand(c->prob, c->st, c->d_params, k & 1, stream);
-    if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 1], stream);
-    if (err == hipSuccess) err = launch_link(c->prob, c->st, c->d_params, k & 1, stream);
-    if (err == hipSuccess) err = hipEventRecord(ev[3 * k + 2], stream);
+    err = launch_demand_timed(c->prob, c->st, c->d_params, k & 1, stream, ev[4 * k], ev[4 * k + 1]);
+    if (err == hipSuccess)
+      err = launch_link_timed(c->prob, c->st, c->d_params, k & 1, stream, ev[4 * k + 2], ev[4 * k + 3]);
   }
   if (err == hipSuccess) err = hipStreamSynchronize(stream);
   double sd = 0.0, sl = 0.0;
   for (int k = 0; k < iters && err == hipSuccess; ++k) {
     float a = 0.f, b = 0.f;
-    err = hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]);
-    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]);
+    err = hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]);
+    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[4 * k + 2], ev[4 * k + 3]);
     sd += a;
     sl += b;
   }
@@ -746,7 +744,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
     for (int k = k1 - 1; k >= k0; --k) {
       const double rho = k > 0 ? lb[k - 1] / lb[k] : 1.0;
       HIPCHK(launch_adj_iteration(c->prob, c->st.nA, c->st.nB, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
-                                  (float)la[k], rho, stream));
+                                  la[k], rho, stream));
     }
   }
   if (!c->rec_warm) HIPCHK(launch_adj_x0(c->prob, a, stream));

@@ -95,6 +95,85 @@ def test_parity_config2_graph(te, c2, K):
     assert err.max() <= REL
 
 
+@pytest.fixture(scope="module")
+def c3_small():
+    # the two-level WAN generator at 6 regions (120 nodes, ~1,150 arcs, 14,280 pairs, k = 4):
+    # same structure as the 1,000-node instance, at a size the oracle runs in a fraction of a second
+    return W.config3(1, regions=6, backbone_links=120)
+
+
+@pytest.mark.parametrize("K", [16, 128])
+def test_parity_hierarchical_graph(te, c3_small, K):
+    r, sb, sa = _oracle_run(c3_small, K)
+    prob = te.Problem(c3_small)
+    x, S, st = _gpu_raw(te, prob, K, sb, sa, te.ENGINE_GRAPH)
+    assert st["iters"] == K
+    err = _report(f"hierarchical graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, c3_small.demand)
+    assert err.max() <= REL
+
+
+_EDGE = {
+    "ragged0": lambda: W.ragged(0),
+    "ragged1": lambda: W.ragged(1, n_links=20, n_demands=70),
+    "one_link_one_demand": lambda: W.shared_link([5.0], cap=1.0),
+    "shared_link": lambda: W.shared_link([0.1, 0.5, 2.0, 8.0], cap=1.0),
+    "parallel_64": lambda: W.parallel_paths(np.linspace(0.5, 2.0, 64), 50.0),
+}
+
+
+@pytest.mark.parametrize("engine", ["block", "graph"])
+@pytest.mark.parametrize("K", [1, 64])
+@pytest.mark.parametrize("name", sorted(_EDGE))
+def test_parity_edge_cases(te, name, engine, K):
+    """Ragged path counts (1..64 per demand), paths longer than the gather batch, unused links,
+    a single link and a single demand, and the widest demand (64 paths on one link each)."""
+    inst = _EDGE[name]()
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
+    x, S, st = _gpu_raw(te, prob, K, sb, sa, eng)
+    assert st["iters"] == K and st["engine"] == eng
+    err = _report(f"{name} {engine} K={K}", S, r.S_raw * r.scale, inst.demand)
+    assert err.max() <= REL
+    # the projected output is feasible on every edge case
+    xp, _, _ = prob.solve(te.Options(fixed_iters=K, engine=eng, sched_beta=sb, sched_alpha=sa))
+    xp = xp.cpu().numpy().astype(np.float64)
+    assert np.all(xp >= 0)
+    assert np.all(O.link_loads(inst, xp) <= inst.capacity * (1 + 1e-7))
+    assert np.all(O.demand_sums(inst, xp) <= inst.demand * (1 + 1e-7))
+
+
+@pytest.mark.parametrize("engine", ["block", "graph"])
+@pytest.mark.parametrize("alpha", [0.0, 1.0, 2.0])
+def test_parity_finite_alpha_targets(te, c1, engine, alpha):
+    """Max-flow (alpha = 0), proportional fairness (1) and alpha = 2 as fixed targets."""
+    K = 400  # with gamma = 0.03 the schedule reaches alpha = 1 at sweep 151 and alpha = 2 at 331
+    r, sb, sa = _oracle_run(c1, K, alpha_target=alpha, gamma=3e-2)
+    assert np.max(sa) == alpha
+    prob = te.Problem(c1)
+    eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
+    x, S, st = _gpu_raw(te, prob, K, sb, sa, eng)
+    err = _report(f"config1 alpha={alpha} {engine}", S, r.S_raw * r.scale, c1.demand)
+    assert err.max() <= REL
+
+
+@pytest.mark.parametrize("engine", ["block", "graph"])
+def test_adaptive_stop_proportional(te, c1, engine):
+    """Adaptive mode (no replay) at alpha_target = 1: the GPU's own residual test stops the solve,
+    near the oracle's stop and at nearly the oracle's allocation."""
+    r = O.solve(c1, O.Options(alpha_target=1.0, gamma=1e-3, max_iters=20000, project=False), want_state=False)
+    assert r.flags & O.CONVERGED
+    prob = te.Problem(c1)
+    eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
+    x, S, st = prob.solve(te.Options(alpha_target=1.0, gamma=1e-3, max_iters=20000, project=False, engine=eng))
+    S = S.cpu().numpy().astype(np.float64)
+    print(f"adaptive alpha=1 {engine}: GPU {st['iters']} iterations, oracle {r.iters}; "
+          f"max |dS|/max D {np.abs(S - r.S_raw * r.scale).max() / c1.demand.max():.2e}")
+    assert st["flags"] & te.TE_CONVERGED and st["final_alpha"] == 1.0
+    assert 0.8 * r.iters <= st["iters"] <= 1.25 * r.iters
+    assert np.abs(S - r.S_raw * r.scale).max() <= 1e-2 * c1.demand.max()
+
+
 @pytest.mark.parametrize("engine", ["block", "graph"])
 def test_projection_config1(te, c1, engine):
     K = 300

@@ -508,3 +508,29 @@ def parallel_paths(caps, demand) -> Instance:
     """One demand over disjoint single-link paths."""
     m = len(caps)
     return make_instance("parallel", 2, [0] * m, [1] * m, caps, [0], [1], [demand], [[[i] for i in range(m)]])
+
+
+def ragged(seed: int = 0, n_links: int = 48, n_demands: int = 40) -> Instance:
+    """Edge-case instance for the kernels' boundaries (not a network): demands with 1, 2, 3, 5, 8, 17,
+    33 and 64 paths (64 is the per-demand maximum), paths of 1 to 12 links (beyond the 8-hop gather
+    batch), one link on a large share of all paths, unused links with zero capacity, and demands
+    spanning four orders of magnitude.  Path link sets are drawn without repeats inside a path."""
+    rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
+    used = n_links - 4  # the last four links carry no path
+    cap = np.concatenate([rng.choice([1.0, 4.0, 10.0], size=used), np.zeros(4)])
+    counts = rng.choice([1, 2, 3, 5, 8, 17, 33, 64], size=n_demands)
+    counts[0], counts[1] = 64, 1
+    paths = []
+    for c in range(n_demands):
+        plist = []
+        for _ in range(int(counts[c])):
+            hops = int(rng.integers(1, 13))
+            links = rng.choice(used - 1, size=hops, replace=False) + 1
+            if rng.uniform() < 0.4:
+                links[0] = 0  # the hot link
+            plist.append(sorted(set(int(e) for e in links)))
+        paths.append(plist)
+    demand = 10.0 ** rng.uniform(-2.0, 2.0, n_demands)
+    src = np.arange(n_links, dtype=np.int32)
+    return make_instance(f"ragged/s{seed}", n_links + 1, src, src + 1, cap, np.zeros(n_demands), np.ones(n_demands),
+                         demand, paths, meta=dict(kind="ragged", seed=seed))
