@@ -40,15 +40,46 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_demand_k_link_150node_traffic.md")
+
+
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("te_kernels.hip", "te_device.h", "te_internal.h"):
+        with open(os.path.join(ROOT, "paper_2605_01748_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
+    each scaled by the same counter's reading for a copy of known size), or None when the summary is
+    missing or was taken on other kernel sources."""
+    import re
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
+        d = json.loads(m.group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_sources_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["traffic_bytes"])
+
+
 def kernel_bytes(inst):
-    """Algorithmic bytes per launch of the two per-iteration kernels (int32 indices, FP32 path state,
-    FP64 per-link / per-demand duals).  Each kernel is charged what it must read or write once:
-      demand kernel: path row pointers 4 (P+1), link ids 4 nnz, x and u_neg read+write 16 P,
-                     per-link (g, q) pairs 16 E, per demand ptr+D 8 + u_dem/S read+write 32 -> 40 D
-      link kernel:   CSC path ids 4 nnz, x read 4 P, (g, q) read+write 32 E, capacity 8 E,
+    """Algorithmic bytes per launch of the two per-iteration kernels (int32 indices, FP64 path state
+    with an FP32 copy of the rates for the link kernel, FP64 per-link / per-demand values).  Each
+    kernel is charged what it must read or write once:
+      demand kernel: path row pointers 4 (P+1), link ids 4 nnz, x and u_neg read+write 32 P, FP32
+                     copy of x written 4 P, per-link (g, q) pairs 16 E, per demand pointer 4 +
+                     D 8 + u_dem and S read+write 32 -> 44 D
+      link kernel:   CSC path ids 4 nnz, FP32 x read 4 P, (g, q) read+write 32 E, capacity 8 E,
                      non-empty link tables 8 E."""
     P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
-    b_dem = 4 * (P + 1) + 4 * nnz + 16 * P + 16 * E + 40 * D
+    b_dem = 4 * (P + 1) + 4 * nnz + 36 * P + 16 * E + 44 * D
     b_link = 4 * nnz + 4 * P + 48 * E
     return b_dem, b_link
 
@@ -82,7 +113,14 @@ def large_run(args, torch, te, W, O, dev):
     iteration of a plain 64-iteration solve, and the error against the FP64 oracle after 16
     iterations with the oracle's schedule replayed (all demands)."""
     t0 = time.time()
-    inst = W.config3(0, cache_dir=args.cache_dir)
+    last = [0.0]
+
+    def progress(done, total):
+        if time.time() - last[0] > 15.0 or done == total:
+            last[0] = time.time()
+            log(f"  k-shortest paths: {done}/{total} pairs ({time.time() - t0:.0f}s)")
+
+    inst = W.config3(0, cache_dir=args.cache_dir, progress=progress)
     log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
     prob = te.Problem(inst)
     ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=32)
@@ -208,7 +246,7 @@ def main():
     dom = ("k_demand", ms_dem, b_dem) if ms_dem * 1 >= ms_link else ("k_link", ms_link, b_link)
     achieved = dom[2] / (dom[1] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom[0],
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom[0]), "kernel": dom[0],
                 "bytes_per_launch": int(dom[2]), "avg_launch_us": round(dom[1] * 1e3, 3),
                 "other_kernel": {"k_demand_us": round(ms_dem * 1e3, 3), "k_link_us": round(ms_link * 1e3, 3),
                                  "k_demand_bytes": int(b_dem), "k_link_bytes": int(b_link)}}
@@ -327,7 +365,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32/f64",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "config2: 150-node Waxman, ~600 links, 22350 gravity demands (lognormal 1.5), "
                                "1.3x max concurrent flow, k=8 latency-shortest paths, max-min target",

@@ -46,7 +46,7 @@ struct Prob {
   const int32_t *dptr;     // [D+1] demand -> path range
   const int32_t *lptr;     // [E+1] link -> CSC range
   const int32_t *lpaths;   // [nnz] path of each CSC entry (link-major, path-ascending)
-  const float *Dn;         // [D] demand
+  const double *Dn;        // [D] demand
   const double *Cn;        // [E] capacity
   // link kernel work split: non-empty links in order (nzlink), their CSC starts (nzptr, one more
   // entry at the end), per-workgroup ranges of non-empty-link ranks (blk[nB+1]); lpf = lpaths
@@ -55,11 +55,15 @@ struct Prob {
   const int32_t *nzlink;
   const int32_t *nzptr;
   const int32_t *blk;
+  // per wavefront of the link kernels ([nB * kLinkWaves]): its CSC entry range [x, y) and the rank
+  // (index into nzlink) of the link holding entry x, precomputed so that no wavefront searches
+  const int4 *wtab;
 };
 
 // Iteration state on the device.
 struct State {
-  float *x, *uneg;   // [P] path rates and non-negativity duals (FP32: the bulk of the state)
+  double *x, *uneg;  // [P] path rates and non-negativity duals
+  float *xf;         // [P] FP32 copy of x, read by the link kernel's gathers (half the bytes)
   double *udem, *S;  // [D] demand duals and last root of the sum equation
   double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
   Ctrl *ctrl;        // [3]
@@ -83,7 +87,7 @@ struct AdjState {
 
 // One stored forward state (the iteration state of State, without control data).
 struct FwdState {
-  float *x, *uneg;
+  double *x, *uneg;
   double *udem, *S;
   double2 *gq;
 };
@@ -92,6 +96,7 @@ constexpr int kMaxLinkBlocks = 512;  // workgroups of the link kernel (partB row
 constexpr int kMaxLinksPerBlock = 1024;
 constexpr int kThreads = 256;        // threads per workgroup of the graph-engine demand kernels
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
+constexpr int kLinkWaves = kLinkThreads / 64;
 constexpr int kBlockThreads = 1024;  // threads of the workgroup engine
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
@@ -115,7 +120,7 @@ struct ProjBuf {
 // Concatenated inputs of the workgroup engine.
 struct Pools {
   const int32_t *i32;  // index pool
-  const float *Dn;     // [sum D]
+  const double *Dn;    // [sum D]
   const double *Cn;    // [sum E]
   const float *x0;     // nullable [sum P] warm start, caller units
 };

@@ -39,12 +39,26 @@ __device__ __forceinline__ void prefetch_ctrl(const State &s, int par, CtrlPrefe
   cp.v[1] = 0.0;
   cp.v[2] = -INFINITY;
   cp.v[3] = -INFINITY;
-  const double *pb = s.partB + (size_t)(par ^ 1) * s.nB * 4;
-  for (int i = threadIdx.x; i < s.nB; i += 64) {
-    cp.v[0] += pb[4 * i + 0];
-    cp.v[1] += pb[4 * i + 1];
-    cp.v[2] = fmax(cp.v[2], pb[4 * i + 2]);
-    cp.v[3] = fmax(cp.v[3], pb[4 * i + 3]);
+  // all rows' loads are issued before the first add (nB <= 8 * 64), so they take one round trip
+  const double2 *pb = reinterpret_cast<const double2 *>(s.partB + (size_t)(par ^ 1) * s.nB * 4);
+  constexpr int R = kMaxLinkBlocks / 64;
+  double2 lo[R], hi[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int i = threadIdx.x + 64 * u;
+    lo[u] = make_double2(0.0, 0.0);
+    hi[u] = make_double2(-INFINITY, -INFINITY);
+    if (i < s.nB) {
+      lo[u] = pb[2 * i];
+      hi[u] = pb[2 * i + 1];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    cp.v[0] += lo[u].x;
+    cp.v[1] += lo[u].y;
+    cp.v[2] = fmax(cp.v[2], hi[u].x);
+    cp.v[3] = fmax(cp.v[3], hi[u].y);
   }
 }
 
@@ -89,21 +103,22 @@ __device__ void block_partials(double p0, double p1, double p2, double p3, doubl
 // ------------------------------------------------------------------------------------------
 // Initialisation (Algorithm 1): x^0 = D_c / |P_c| or the warm start, duals zero, y^0 = x^0.
 // ------------------------------------------------------------------------------------------
-__global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, float inv_scale) {
+__global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, double inv_scale) {
   const Params &prm = *prmp;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
     const int r0 = p.dptr[c], r1 = p.dptr[c + 1];
-    float sum = 0.f;
+    double sum = 0.0;
     for (int r = r0; r < r1; ++r) {
-      float v = x0 ? x0[r] * inv_scale : p.Dn[c] / (float)(r1 - r0);
+      const double v = x0 ? (double)x0[r] * inv_scale : p.Dn[c] / (double)(r1 - r0);
       s.x[r] = v;
-      s.uneg[r] = 0.f;
+      s.xf[r] = (float)v;
+      s.uneg[r] = 0.0;
       sum += v;
     }
     s.udem[c] = 0.0;
-    s.S[c] = (double)sum;
+    s.S[c] = sum;
   }
   for (int e = tid; e < p.E; e += nth) s.gq[e] = make_double2(0.0, 0.0);
   if (tid == 0) {
@@ -128,7 +143,7 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
   // gathers (independent of the control record): sums of g and q along the path
   int r0 = 0, np = 0, r = 0, n = 1;
-  float xr = 0.f, ung = 0.f, Dc = 0.f;
+  double xr = 0.0, ung = 0.0, Dc = 0.0;
   double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
   bool on = false;
   if (c < p.D) {
@@ -166,27 +181,28 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   if (c < p.D) {
     Lane L;
     L.on = on;
-    L.a = on ? (double)n * (double)xr - (sg * inv_f - sq) : 0.0;
-    L.un = (double)ung * inv_f;
+    L.a = on ? (double)n * xr - (sg * inv_f - sq) : 0.0;
+    L.un = ung * inv_f;
     L.n = (double)n;
     L.rn = 1.0 / (double)n;
     L.rn1 = 1.0 / (double)(n + 1);
     Dem dm;
-    dm.D = (double)Dc;
+    dm.D = Dc;
     dm.u = udc * inv_f;
     dm.alpha = cs.alpha;
     dm.binv = 1.0 / cs.beta;
     int steps;
     const double Sst = sum_root(S0, L, dm, G, &steps);
     const double h = h_of(Sst, dm);
-    const float xn = L.on ? (float)xi_of(L.a - h, L) : 0.f;
-    const double Ssum = group_sum_d((double)xn, G);
+    const double xn = L.on ? xi_of(L.a - h, L) : 0.0;
+    const double Ssum = group_sum_d(xn, G);
     if (L.on) {
-      const float un = (float)fmax(L.un - (double)xn, 0.0);
+      const double un = fmax(L.un - xn, 0.0);
       s.x[r] = xn;
+      s.xf[r] = (float)xn;
       s.uneg[r] = un;
-      ds2 = (double)(xn - xr) * (double)(xn - xr);
-      dr2 = ((double)un - L.un) * ((double)un - L.un);
+      ds2 = (xn - xr) * (xn - xr);
+      dr2 = (un - L.un) * (un - L.un);
     }
     if (lane == 0) {
       const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
@@ -199,24 +215,17 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
 }
 
-// Segmented sums over the CSC entries of the non-empty links k0..k1-1 owned by this workgroup:
-// acc[k - k0] += sum of vals[path] over the entries of link nzlink[k].  Each wavefront walks a
-// contiguous part in coalesced rows of 64 entries; runs of equal link in a row are reduced by a
+// Segmented sums over the CSC entries of the non-empty links owned by this workgroup (ranks k0..):
+// acc[k - k0] += sum of vals[path] over the entries of link nzlink[k].  Each wavefront walks its
+// contiguous part wt = {first entry, end, rank of the link holding the first entry} of the
+// workgroup's entries in coalesced rows of 64; runs of equal link in a row are reduced by a
 // segmented scan and their tail lane adds one partial into the LDS accumulator.
 template <class T>
-__device__ __forceinline__ void seg_rows_sum(const Prob &p, const T *vals, int k0, int k1, double *acc) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  const int j0 = p.nzptr[k0], j1 = p.nzptr[k1];
-  const int len = j1 - j0, per = (len + nw - 1) / nw;
-  const int ja = j0 + min(len, w * per), jb = j0 + min(len, (w + 1) * per);
+__device__ __forceinline__ void seg_rows_sum(const Prob &p, const T *vals, int k0, int4 wt, double *acc) {
+  const int lane = threadIdx.x & 63;
+  const int ja = wt.x, jb = wt.y;
   if (ja >= jb) return;
-  int lo = k0, hi = k1 - 1;  // rank of the link holding entry ja
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (p.nzptr[mid] <= ja) lo = mid; else hi = mid - 1;
-  }
-  int kbase = lo;
+  int kbase = wt.z;
   constexpr int U = 4;  // rows whose loads are issued together
   for (int j = ja; j < jb; j += 64 * U) {
     int32_t v[U];
@@ -262,6 +271,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   CtrlPrefetch cp;
   if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int4 wt = p.wtab[blockIdx.x * kLinkWaves + w];
   const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   // the per-link values of this thread's first link and its slice of the demand kernel's
@@ -286,7 +296,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     }
   }
   __syncthreads();
-  seg_rows_sum(p, s.x, k0, k1, acc);
+  seg_rows_sum(p, s.xf, k0, wt, acc);
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -428,6 +438,8 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
   __shared__ uint64_t kred[4];
   __shared__ double xred[4];
   __shared__ uint64_t keyT;
+  __shared__ unsigned long long aboveT;
+  __shared__ unsigned long long hist[256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int e = blockIdx.x; e < p.E; e += gridDim.x) {
     const double V = b.L[e] - p.Cn[e];
@@ -473,26 +485,70 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
       continue;
     }
     // general case: threshold key K* where the descending cumulative rate reaches V,
-    // f(T) = sum of x over incidences with key >= T; the largest T with f(T) >= V
-    uint64_t lo = 0ull, hi = ~0ull;
-    for (int bit = 0; bit < 64; ++bit) {
-      const uint64_t mid = lo + ((hi - lo) >> 1) + ((hi - lo) & 1ull);
-      double acc = 0.0;
+    // f(T) = sum of x over incidences with key >= T; the largest T with f(T) >= V.  Radix
+    // selection from the top byte down: per pass a 256-bucket histogram of the rates of the keys
+    // that share the bytes chosen so far, summed in 64-bit fixed point (exact and independent
+    // of the order of the atomic adds, so the choice is deterministic); scale 2^sh with
+    // L_e * 2^sh < 2^62, so no partial sum overflows.
+    int ex2;
+    (void)frexp(b.L[e], &ex2);
+    const int sh = 62 - ex2;
+    const unsigned long long Vq = (unsigned long long)ceil(ldexp(V, sh));
+    uint64_t prefix = 0ull;
+    unsigned long long above_q = 0ull;
+    for (int pass = 0; pass < 8; ++pass) {
+      const int shift = 56 - 8 * pass;
+      const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));  // bytes chosen so far
+      hist[threadIdx.x] = 0ull;  // blockDim.x == 256
+      __syncthreads();
       for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
         const int r = p.lpaths[j];
-        if (trim_key(b.lsc[r], r) >= mid) acc += b.xd[r];
+        const uint64_t k = trim_key(b.lsc[r], r);
+        if (((k ^ prefix) & hmask) == 0ull)
+          atomicAdd(&hist[(k >> shift) & 255ull], (unsigned long long)ldexp(b.xd[r], sh));
       }
-      acc = wave_sum_d(acc);
-      if (lane == 0) red[w] = acc;
       __syncthreads();
-      const double f = red[0] + red[1] + red[2] + red[3];
+      if (w == 0) {
+        // lane l holds digits 255-4l .. 252-4l, i.e. the buckets in descending digit order
+        unsigned long long hv[4], tot = 0ull;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hv[i] = hist[255 - 4 * lane - i];
+          tot += hv[i];
+        }
+        unsigned long long inc = tot;  // inclusive prefix over lanes (higher digits first)
+        for (int d = 1; d < 64; d <<= 1) {
+          const unsigned long long y = __shfl_up(inc, d, 64);
+          if (lane >= d) inc += y;
+        }
+        unsigned long long cum = above_q + (inc - tot);  // rate of the keys above this lane's digits
+        int dig = -1;
+        unsigned long long cum_at = 0ull;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (dig < 0 && cum + hv[i] >= Vq) {
+            dig = 255 - 4 * lane - i;
+            cum_at = cum;
+          }
+          cum += hv[i];
+        }
+        const uint64_t hit = __ballot(dig >= 0);
+        const int src = hit ? __ffsll((unsigned long long)hit) - 1 : 63;
+        if (!hit && lane == 63) {  // rounding left f(0) below V: digit 0, all higher digits above
+          dig = 0;
+          cum_at = above_q + (inc - hv[3]);
+        }
+        if (lane == src) {
+          keyT = prefix | ((uint64_t)dig << shift);
+          aboveT = cum_at;
+        }
+      }
       __syncthreads();
-      if (f >= V) lo = mid; else hi = mid - 1;
-      if (lo >= hi) break;
+      prefix = keyT;
+      above_q = aboveT;
+      __syncthreads();
     }
-    if (threadIdx.x == 0) keyT = lo;
-    __syncthreads();
-    const uint64_t T = keyT;
+    const uint64_t T = prefix;
     double acc = 0.0;
     for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
       const int r = p.lpaths[j];
@@ -516,7 +572,7 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
 }
 
 // step 6 and outputs in caller units (rounded toward zero: the FP32 rates stay feasible)
-__global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double scale, int project, const float *xs) {
+__global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double scale, int project, const double *xs) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
@@ -528,7 +584,7 @@ __global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double 
         v = fmax(v, 0.0) * scale;
         x_out[r] = __double2float_rz(v);
       } else {
-        v = (double)xs[r] * scale;
+        v = xs[r] * scale;
         x_out[r] = (float)v;
       }
       sum += (double)x_out[r];
@@ -555,9 +611,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   double *Lx = Cn + E;                               // E  (loads, FP64)
   double *udem = Lx + E;                             // D
   double *S = udem + D;                              // D
-  float *x = (float *)(S + D);                       // P
-  float *uneg = x + P;                               // P
-  float *Dn = uneg + P;                              // D
+  double *x = S + D;                                 // P
+  double *uneg = x + P;                              // P
+  double *Dn = uneg + P;                             // D
   int32_t *pptr = (int32_t *)(Dn + D);               // P + 1
   int32_t *plinks = pptr + P + 1;                    // nnz
   int32_t *dptr = plinks + nnz;                      // D + 1
@@ -576,18 +632,18 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   }
   for (int i = tid; i < D; i += nth) Dn[i] = pools.Dn[d.off_D + i];
   __syncthreads();
-  const float inv_scale = (float)(1.0 / d.scale);
+  const double inv_scale = 1.0 / d.scale;
   for (int c = tid; c < D; c += nth) {
     const int r0 = dptr[c], r1 = dptr[c + 1];
-    float sum = 0.f;
+    double sum = 0.0;
     for (int r = r0; r < r1; ++r) {
-      const float v = pools.x0 ? pools.x0[d.off_P + r] * inv_scale : Dn[c] / (float)(r1 - r0);
+      const double v = pools.x0 ? (double)pools.x0[d.off_P + r] * inv_scale : Dn[c] / (double)(r1 - r0);
       x[r] = v;
-      uneg[r] = 0.f;
+      uneg[r] = 0.0;
       sum += v;
     }
     udem[c] = 0.0;
-    S[c] = (double)sum;
+    S[c] = sum;
   }
   if (tid == 0) cs = initial_ctrl(prm);
   __syncthreads();
@@ -609,7 +665,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
         Lane L;
         L.on = lane < np;
         const int r = r0 + (L.on ? lane : 0);
-        float xr = 0.f;
+        double xr = 0.0;
         int n = 1;
         L.a = 0.0;
         L.un = 0.0;
@@ -623,25 +679,25 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
             sq += v.y;
           }
           xr = x[r];
-          L.a = (double)n * (double)xr - (sg * inv_f - sq);
-          L.un = (double)uneg[r] * inv_f;
+          L.a = (double)n * xr - (sg * inv_f - sq);
+          L.un = uneg[r] * inv_f;
         }
         L.n = (double)n;
         L.rn = 1.0 / (double)n;
         L.rn1 = 1.0 / (double)(n + 1);
-        dm.D = (double)Dn[c];
+        dm.D = Dn[c];
         dm.u = udem[c] * inv_f;
         int steps;
         const double Sst = sum_root(S[c], L, dm, G, &steps);
         const double h = h_of(Sst, dm);
-        const float xn = L.on ? (float)xi_of(L.a - h, L) : 0.f;
-        const double Ssum = group_sum_d((double)xn, G);
+        const double xn = L.on ? xi_of(L.a - h, L) : 0.0;
+        const double Ssum = group_sum_d(xn, G);
         if (L.on) {
-          const float un = (float)fmax(L.un - (double)xn, 0.0);
+          const double un = fmax(L.un - xn, 0.0);
           x[r] = xn;
           uneg[r] = un;
-          ds2 += (double)(xn - xr) * (double)(xn - xr);
-          dr2 += ((double)un - L.un) * ((double)un - L.un);
+          ds2 += (xn - xr) * (xn - xr);
+          dr2 += (un - L.un) * (un - L.un);
         }
         if (lane == 0) {
           const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
@@ -657,7 +713,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
     for (int e = w; e < E; e += nw) {
       const int j0 = lptr[e], j1 = lptr[e + 1];
       double acc = 0.0;
-      for (int j = j0 + l64; j < j1; j += 64) acc += (double)x[lpaths[j]];
+      for (int j = j0 + l64; j < j1; j += 64) acc += x[lpaths[j]];
       acc = wave_sum_d(acc);
       if (l64 == 0 && j1 > j0) {
         const double2 v = gq[e];
@@ -697,25 +753,25 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   }
 
   // ---------------- Algorithm 2 (if requested) ----------------
-  // x (LDS) holds the working rates; per-path log scores go to uneg; per-path trims of the
+  // x (LDS) holds the working rates; per-path log scores (FP32 values) go to uneg; per-path trims of the
   // link phase are combined by max in x_out (float bits of non-negative values).
   const float alpha = (float)cs.alpha;
   float *xo = x_out + d.off_P;
   for (int r = tid; r < P; r += nth) xo[r] = 0.f;
   if (project) {
-    for (int r = tid; r < P; r += nth) x[r] = fmaxf(x[r], 0.f);
+    for (int r = tid; r < P; r += nth) x[r] = fmax(x[r], 0.0);
     __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
       for (int e = w; e < E; e += nw) {
         double acc = 0.0;
-        for (int j = lptr[e] + l64; j < lptr[e + 1]; j += 64) acc += (double)x[lpaths[j]];
+        for (int j = lptr[e] + l64; j < lptr[e + 1]; j += 64) acc += x[lpaths[j]];
         acc = wave_sum_d(acc);
         if (l64 == 0) Lx[e] = acc;
       }
       __syncthreads();
       for (int c = tid; c < D; c += nth) {
         double sum = 0.0;
-        for (int r = dptr[c]; r < dptr[c + 1]; ++r) sum += (double)x[r];
+        for (int r = dptr[c]; r < dptr[c + 1]; ++r) sum += x[r];
         for (int r = dptr[c]; r < dptr[c + 1]; ++r) {
           int k = 0;
           for (int i = pptr[r]; i < pptr[r + 1]; ++i) k += Lx[plinks[i]] > Cn[plinks[i]];
@@ -724,17 +780,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
         if (pass == 0) {
           // demand phase: trim the excess over D_c in descending score
           const int r0 = dptr[c], r1 = dptr[c + 1];
-          double excess = sum - (double)Dn[c];
+          double excess = sum - Dn[c];
           uint64_t done = 0ull;
           for (int it = 0; it < r1 - r0 && excess > 0.0; ++it) {
             int best = -1;
             for (int r = r0; r < r1; ++r) {
               if (done >> (r - r0) & 1ull) continue;
-              if (best < 0 || trim_key(uneg[r], r) > trim_key(uneg[best], best)) best = r;
+              if (best < 0 || trim_key((float)uneg[r], r) > trim_key((float)uneg[best], best)) best = r;
             }
             done |= 1ull << (best - r0);
-            const double dd = fmin(excess, (double)x[best]);
-            x[best] = __double2float_rz((double)x[best] - dd);
+            const double dd = fmin(excess, x[best]);
+            x[best] = x[best] - dd;
             excess -= dd;
           }
         }
@@ -749,13 +805,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
       const int j0 = lptr[e], j1 = lptr[e + 1];
       for (int j = j0 + l64; j < j1; j += 64) {
         const int r = lpaths[j];
-        const uint64_t kr = trim_key(uneg[r], r);
+        const uint64_t kr = trim_key((float)uneg[r], r);
         double before = 0.0;
         for (int i = j0; i < j1; ++i) {
           const int q = lpaths[i];
-          if (trim_key(uneg[q], q) > kr) before += (double)x[q];
+          if (trim_key((float)uneg[q], q) > kr) before += x[q];
         }
-        const double dd = fmin((double)x[r], fmax(V - before, 0.0));
+        const double dd = fmin(x[r], fmax(V - before, 0.0));
         // rounded up, so that the FP32 trim removes at least the link's share of the excess
         if (dd > 0.0) atomicMax((unsigned int *)&xo[r], __float_as_uint(__double2float_ru(dd)));
       }
@@ -767,7 +823,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   for (int c = tid; c < D; c += nth) {
     double sum = 0.0;
     for (int r = dptr[c]; r < dptr[c + 1]; ++r) {
-      double v = (double)x[r];
+      double v = x[r];
       if (project) v = fmax(v - (double)xo[r], 0.0);
       const float o = project ? __double2float_rz(v * scale) : (float)(v * scale);
       xo[r] = o;
@@ -878,10 +934,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, F
 
 __global__ __launch_bounds__(kLinkThreads) void k_adj_link(Prob p, FwdState fout, AdjState a, double rho) {
   __shared__ double acc[kMaxLinksPerBlock];
+  const int4 wt = p.wtab[blockIdx.x * kLinkWaves + (threadIdx.x >> 6)];
   const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   __syncthreads();
-  seg_rows_sum(p, a.ab, k0, k1, acc);
+  seg_rows_sum(p, a.ab, k0, wt, acc);
   __syncthreads();
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const int e = p.nzlink[k];
@@ -950,7 +1007,7 @@ hipError_t launch_adj_x0(const Prob &p, const AdjState &a, hipStream_t st) {
 // ------------------------------------------------------------------------------------------
 // host-side launchers
 // ------------------------------------------------------------------------------------------
-hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const float *x0, float inv_scale,
+hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const float *x0, double inv_scale,
                        hipStream_t st) {
   int n = p.D > p.E ? p.D : p.E;
   int blocks = (n + 255) / 256;
@@ -1014,7 +1071,7 @@ hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools,
 }
 
 size_t block_lds_bytes(int E, int P, int D, int nnz) {
-  return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 4) + (size_t)P * 4 * 2 +
+  return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 8) + (size_t)P * 8 * 2 +
          (size_t)4 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz) + 16;
 }
 

@@ -18,7 +18,7 @@
 #include "te_internal.h"
 
 namespace te {
-hipError_t launch_init(const Prob &, const State &, const Params *, const float *, float, hipStream_t);
+hipError_t launch_init(const Prob &, const State &, const Params *, const float *, double, hipStream_t);
 hipError_t launch_iteration(const Prob &, const State &, const Params *, int, hipStream_t);
 hipError_t launch_demand_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
 hipError_t launch_link_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
@@ -73,7 +73,7 @@ struct te_ctx {
   std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
   std::vector<int32_t> lpf, nzlink, nzptr, blk;  // link-kernel work split
   std::vector<double> cap, dem;  // caller units
-  std::vector<float> Dn;
+  std::vector<double> Dn;
   std::vector<double> Cn;
   // device
   Prob prob{};
@@ -85,7 +85,8 @@ struct te_ctx {
   double *d_sched = nullptr;
   int32_t sched_cap = 0;
   int32_t *d_i32 = nullptr;
-  float *d_Dn = nullptr;
+  int4 *d_wtab = nullptr;
+  double *d_Dn = nullptr;
   double *d_Cn = nullptr;
   // workgroup engine (single instance)
   BatchDesc *d_desc = nullptr;
@@ -116,7 +117,7 @@ struct te_batch {
   BatchDesc *d_desc = nullptr;
   BatchOut *d_out = nullptr;
   int32_t *d_i32 = nullptr;
-  float *d_Dn = nullptr;
+  double *d_Dn = nullptr;
   double *d_Cn = nullptr;
   Params *d_params = nullptr;
   Params *h_params = nullptr;
@@ -208,13 +209,13 @@ void normalise(te_ctx *c) {
   c->Cn.resize(c->E);
   c->Dn.resize(c->D);
   for (int32_t e = 0; e < c->E; ++e) c->Cn[e] = c->cap[e] / s;
-  for (int32_t k = 0; k < c->D; ++k) c->Dn[k] = (float)(c->dem[k] / s);
+  for (int32_t k = 0; k < c->D; ++k) c->Dn[k] = c->dem[k] / s;
 }
 
 te_status upload_values(te_ctx *c) {
   HIPCHK(hipSetDevice(c->device));
   HIPCHK(hipMemcpy(c->d_Cn, c->Cn.data(), sizeof(double) * c->E, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->d_Dn, c->Dn.data(), sizeof(float) * c->D, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->d_Dn, c->Dn.data(), sizeof(double) * c->D, hipMemcpyHostToDevice));
   BatchDesc d{};
   d.E = c->E;
   d.P = c->P;
@@ -322,8 +323,8 @@ void free_fwd(FwdState &f) {
 FwdState fwd_of(const State &s) { return FwdState{s.x, s.uneg, s.udem, s.S, s.gq}; }
 
 hipError_t copy_fwd(const FwdState &dst, const FwdState &src, const te_ctx *c, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(dst.x, src.x, sizeof(float) * c->P, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst.uneg, src.uneg, sizeof(float) * c->P, hipMemcpyDeviceToDevice, st);
+  hipError_t e = hipMemcpyAsync(dst.x, src.x, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dst.uneg, src.uneg, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dst.udem, src.udem, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dst.S, src.S, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dst.gq, src.gq, sizeof(double2) * c->E, hipMemcpyDeviceToDevice, st);
@@ -410,6 +411,19 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     c->blk.push_back((int32_t)c->nzlink.size());
   }
   const int nB = (int)c->blk.size() - 1;
+  // per-wavefront parts of each workgroup's CSC entries (the split the link kernels use)
+  std::vector<int4> wtab((size_t)nB * kLinkWaves);
+  for (int b = 0; b < nB; ++b) {
+    const int32_t k0 = c->blk[b], k1 = c->blk[b + 1];
+    const int32_t j0 = c->nzptr[k0], len = c->nzptr[k1] - j0;
+    const int32_t per = (len + kLinkWaves - 1) / kLinkWaves;
+    int32_t k = k0;
+    for (int w = 0; w < kLinkWaves; ++w) {
+      const int32_t ja = j0 + std::min(len, w * per), jb = j0 + std::min(len, (w + 1) * per);
+      while (k + 1 < k1 && c->nzptr[k + 1] <= ja) ++k;
+      wtab[(size_t)b * kLinkWaves + w] = make_int4(ja, jb, k, 0);
+    }
+  }
   c->maxp = 0;
   for (int32_t k = 0; k < n_demands; ++k) c->maxp = std::max(c->maxp, c->dptr[k + 1] - c->dptr[k]);
   c->G = 1;
@@ -431,7 +445,7 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
                     c->nzptr.size() + c->blk.size();
   const int nA = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
-            dalloc(&c->d_Cn, c->E) == hipSuccess && dalloc(&c->st.x, c->P) == hipSuccess &&
+            dalloc(&c->d_Cn, c->E) == hipSuccess && dalloc(&c->st.x, c->P) == hipSuccess && dalloc(&c->st.xf, c->P) == hipSuccess &&
             dalloc(&c->st.uneg, c->P) == hipSuccess && dalloc(&c->st.udem, c->D) == hipSuccess &&
             dalloc(&c->st.S, c->D) == hipSuccess && dalloc(&c->st.gq, c->E) == hipSuccess &&
             dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA * 4) == hipSuccess &&
@@ -440,8 +454,10 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
             dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
             dalloc(&c->pb.lsc, c->P) == hipSuccess && dalloc(&c->pb.trim, c->P) == hipSuccess &&
             dalloc(&c->d_params, 1) == hipSuccess && dalloc(&c->d_desc, 1) == hipSuccess &&
-            dalloc(&c->d_bout, 1) == hipSuccess;
+            dalloc(&c->d_bout, 1) == hipSuccess && dalloc(&c->d_wtab, wtab.size()) == hipSuccess;
   if (!ok) return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
+  if (hipMemcpy(c->d_wtab, wtab.data(), sizeof(int4) * wtab.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the link work table failed"));
   if (hipHostMalloc((void **)&c->h_params, sizeof(Params)) != hipSuccess ||
       hipHostMalloc((void **)&c->h_flag, sizeof(int32_t) * 4) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_OOM, "pinned host allocation failed"));
@@ -484,6 +500,7 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.nzlink = p.lpf + c->nnz;
   p.nzptr = p.nzlink + c->nzlink.size();
   p.blk = p.nzptr + c->nzptr.size();
+  p.wtab = c->d_wtab;
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -541,7 +558,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   } else {
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
-    HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, (float)(1.0 / c->scale), stream));
+    HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, 1.0 / c->scale, stream));
     int launched = 0;
     if (o.record) {
       // plain launches with the (beta, alpha) log; the gradient pass replays it
@@ -643,7 +660,7 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
         if (f) (void)hipEventDestroy(f);
       return fail(TE_ERR_DEVICE, "event creation failed");
     }
-  hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, (float)(1.0 / c->scale), stream);
+  hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, 1.0 / c->scale, stream);
   for (int k = 0; k < iters && err == hipSuccess; ++k) {
     err = launch_demand_timed(c->prob, c->st, c->d_params, k & 1, stream, ev[4 * k], ev[4 * k + 1]);
     if (err == hipSuccess)
@@ -719,7 +736,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
   const FwdState work = fwd_of(c->st);
   // forward pass with checkpoints every ck iterations (state + the control record read by the next iteration)
-  HIPCHK(launch_init(c->prob, c->st, c->d_params, c->rec_warm ? c->d_x0rec : nullptr, (float)(1.0 / c->scale),
+  HIPCHK(launch_init(c->prob, c->st, c->d_params, c->rec_warm ? c->d_x0rec : nullptr, 1.0 / c->scale,
                      stream));
   for (int k = 0; k < K; ++k) {
     if (k % ck == 0) {
@@ -764,9 +781,9 @@ void te_destroy(te_ctx *c) {
     for (void *p : ab)
       if (p) (void)hipFree(p);
   }
-  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.x, c->st.uneg, c->st.udem, c->st.S, c->st.gq, c->st.ctrl,
+  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.x, c->st.xf, c->st.uneg, c->st.udem, c->st.S, c->st.gq, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
-                  c->d_params, c->d_desc, c->d_bout, c->d_sched};
+                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_params) (void)hipHostFree(c->h_params);
@@ -791,7 +808,7 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
   b->device = dev;
   b->n = n;
   std::vector<int32_t> pool;
-  std::vector<float> Dn;
+  std::vector<double> Dn;
   std::vector<double> Cn;
   int64_t offE = 0, offP = 0, offD = 0;
   for (int32_t k = 0; k < n; ++k) {
@@ -851,7 +868,7 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
     return bail(fail(TE_ERR_DEVICE, "event creation failed"));
   if (hipMemcpy(b->d_desc, b->desc.data(), sizeof(BatchDesc) * n, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_i32, pool.data(), sizeof(int32_t) * pool.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_Dn, Dn.data(), sizeof(float) * Dn.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_Dn, Dn.data(), sizeof(double) * Dn.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_Cn, Cn.data(), sizeof(double) * Cn.size(), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(TE_ERR_DEVICE, "batch upload failed"));
   *out = b;

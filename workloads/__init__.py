@@ -139,9 +139,10 @@ def build_ksp() -> str:
     return out
 
 
-def k_shortest_paths_csr(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, k, chunk=8192):
+def k_shortest_paths_csr(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, k, chunk=8192, progress=None):
     """Vectorised variant for large pair sets: returns (paths per pair [npairs], path_ptr [P+1] int64,
-    path_links [nnz] int32), paths of a pair contiguous and in (cost, sequence) order."""
+    path_links [nnz] int32), paths of a pair contiguous and in (cost, sequence) order.  progress, if
+    given, is called with (pairs done, pairs total) after every chunk."""
     arc_src = np.ascontiguousarray(arc_src, dtype=np.int32)
     arc_dst = np.ascontiguousarray(arc_dst, dtype=np.int32)
     weight = np.ascontiguousarray(weight, dtype=np.float64)
@@ -179,6 +180,8 @@ def k_shortest_paths_csr(n_nodes, arc_src, arc_dst, weight, pair_src, pair_dst, 
         counts.append(npaths)
         hops_all.append(h)
         links_all.append(arcs[idx])
+        if progress is not None:
+            progress(s1, pair_src.shape[0])
     counts = np.concatenate(counts)
     hops = np.concatenate(hops_all)
     path_ptr = np.concatenate([[0], np.cumsum(hops)]).astype(np.int64)
@@ -374,7 +377,8 @@ def config2(seed: int = 0) -> Instance:
 
 
 def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_links: int = 80, gateways: int = 4,
-            backbone_links: int = 1000, k: int = 4, factor: float = 1.3, cache_dir: str | None = None) -> Instance:
+            backbone_links: int = 1000, k: int = 4, factor: float = 1.3, cache_dir: str | None = None,
+            progress=None) -> Instance:
     """Hierarchical WAN: `regions` Waxman regions of `region_nodes` nodes (~`region_links` links each,
     capacities {100, 400}) in their own unit sub-squares of a 10 x 5 layout, joined by a Waxman
     backbone over `gateways` gateway nodes per region (~`backbone_links` links, capacities
@@ -426,7 +430,7 @@ def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_lin
     ps, pt = np.nonzero(~np.eye(n, dtype=bool))
     ps = ps.astype(np.int32)
     pt = pt.astype(np.int32)
-    counts, path_ptr, path_links = k_shortest_paths_csr(n, src, dst, wgt, ps, pt, k)
+    counts, path_ptr, path_links = k_shortest_paths_csr(n, src, dst, wgt, ps, pt, k, progress=progress)
     keep = counts > 0
     ps, pt = ps[keep], pt[keep]
     base = gravity(w, ps, pt)
