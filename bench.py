@@ -298,7 +298,8 @@ def main():
         probs = [te.Problem(s) for s in scen]
         bt = te.Batch(probs)
         o1 = te.Options(fixed_iters=K1)
-        bt.solve(o1, stats=False)
+        _, _, st_b = bt.solve(o1)  # the first batch solve also picks the workgroup size
+        wg = st_b[0]["block_threads"]
         torch.cuda.synchronize()
         tb = time.perf_counter()
         reps = 3
@@ -317,7 +318,7 @@ def main():
         t_plain = (time.perf_counter() - tp) / n_plain
         batch = {"scenarios": len(probs), "K": K1, "batched_scenarios_per_s": round(len(probs) / t_batch, 1),
                  "plain_scenarios_per_s": round(1.0 / t_plain, 1),
-                 "speedup": round((len(probs) / t_batch) * t_plain, 2),
+                 "speedup": round((len(probs) / t_batch) * t_plain, 2), "batch_workgroup_threads": wg,
                  "workload": "config-1 topology, 1-3 link cuts, lognormal(0,0.3) demand noise, k_c in 2..8"}
         log(f"batch: {batch} ({time.time() - t2:.1f}s)")
 

@@ -92,6 +92,9 @@ typedef struct {
   int32_t engine;      /* TE_ENGINE_* */
   int32_t record;      /* 1: keep the (beta, alpha) schedule and checkpoints for te_grad */
   int32_t ckpt_every;  /* te_grad checkpoint spacing in iterations; default 16 */
+  int32_t block_threads; /* workgroup engine: threads per workgroup, 256, 512 or 1024; 0 (default):
+                            1024 for single solves, and for batches the fastest of the three measured
+                            on the batch's first solve (kept by the batch handle) */
   /* Optional replay of a (beta_k, alpha_k) schedule, host arrays of sched_len entries: iteration k
    * uses beta = sched_beta[k], alpha = sched_alpha[k] (the last entry repeats), no adaptation. */
   const double *sched_beta;
@@ -104,6 +107,7 @@ typedef struct {
   int32_t flags;       /* TE_CONVERGED | ... */
   int32_t stop_iter;   /* first iteration at which the stop test passed, -1 if never */
   int32_t engine;      /* engine that ran */
+  int32_t block_threads; /* workgroup engine: threads per workgroup that ran (0 for the graph engine) */
   double final_alpha;
   double beta;         /* final penalty */
   double r, s;         /* last primal and dual residuals (section 3.4) */

@@ -36,13 +36,14 @@ class _Options(ctypes.Structure):
                 ("beta_max", ctypes.c_double), ("max_iters", ctypes.c_int32), ("alpha_max", ctypes.c_int32),
                 ("fixed_iters", ctypes.c_int32), ("adapt_beta", ctypes.c_int32), ("beta_every", ctypes.c_int32),
                 ("project", ctypes.c_int32), ("engine", ctypes.c_int32), ("record", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("sched_beta", ctypes.c_void_p), ("sched_alpha", ctypes.c_void_p),
-                ("sched_len", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("sched_beta", ctypes.c_void_p),
+                ("sched_alpha", ctypes.c_void_p), ("sched_len", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("stop_iter", ctypes.c_int32),
-                ("engine", ctypes.c_int32), ("final_alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("engine", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("final_alpha", ctypes.c_double),
+                ("beta", ctypes.c_double),
                 ("r", ctypes.c_double), ("s", ctypes.c_double), ("max_cap_viol_rel", ctypes.c_double),
                 ("max_dem_viol_rel", ctypes.c_double), ("ms", ctypes.c_double)]
 
@@ -117,6 +118,7 @@ class Options:
     engine: int = ENGINE_AUTO
     record: bool = False
     ckpt_every: int = 16
+    block_threads: int = 0             # workgroup engine: 256, 512, 1024; 0 = default / tuned for batches
     sched_beta: np.ndarray | None = None
     sched_alpha: np.ndarray | None = None
 
@@ -139,6 +141,7 @@ class Options:
         o.engine = self.engine
         o.record = int(self.record)
         o.ckpt_every = self.ckpt_every
+        o.block_threads = self.block_threads
         keep = []
         if self.sched_beta is not None:
             sb = np.ascontiguousarray(self.sched_beta, np.float64)

@@ -135,7 +135,8 @@ __device__ __forceinline__ double xi_of(double b, const Lane &L) {
 }
 
 __device__ __forceinline__ double h_of(double S, const Dem &c) {
-  return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, 1.0 / S, c.alpha) * c.binv;
+  const double invS = c.alpha > 0.0 ? 1.0 / S : 0.0;  // alpha = 0: S^-alpha = 1, no division
+  return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, invS, c.alpha) * c.binv;
 }
 
 // F(S) and F'(S) summed over the group (uniform inside the group).
@@ -146,7 +147,7 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
     return;
   }
   const double t = S - c.D + c.u;
-  const double invS = 1.0 / S;
+  const double invS = c.alpha > 0.0 ? 1.0 / S : 0.0;  // alpha = 0: S^-alpha = 1, no division
   const double pw = pow_neg_alpha(S, invS, c.alpha);
   const double h = fmax(t, 0.0) - pw * c.binv;
   const double dh = (t > 0.0 ? 1.0 : 0.0) + (c.alpha > 0.0 ? c.alpha * pw * c.binv * invS : 0.0);

@@ -97,12 +97,15 @@ constexpr int kMaxLinksPerBlock = 1024;
 constexpr int kThreads = 256;        // threads per workgroup of the graph-engine demand kernels
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kLinkWaves = kLinkThreads / 64;
-constexpr int kBlockThreads = 1024;  // threads of the workgroup engine
+constexpr int kBlockThreads = 1024;  // threads of the workgroup engine for single solves
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
 struct BatchDesc {
   int32_t E, P, D, nnz, G, logG;
-  int64_t off_pptr, off_plinks, off_dptr, off_lptr, off_lpaths;  // into int32 pools
+  int32_t nzl;  // non-empty links
+  // into int32 pools: CSR, demand ranges, CSC pointers, CSC path ids with bit 31 on each link's
+  // first entry, the non-empty links in order
+  int64_t off_pptr, off_plinks, off_dptr, off_lptr, off_lpf, off_nzl;
   int64_t off_E, off_P, off_D;  // element offsets of per-link / per-path / per-demand arrays
   double scale;
 };

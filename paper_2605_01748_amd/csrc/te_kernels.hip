@@ -215,36 +215,43 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
 }
 
+// CSC entry encodings: int32 (graph engine) with bit 31 on a link's first entry, uint16 (workgroup
+// engine, LDS) with bit 15 on it.
+__device__ __forceinline__ bool csc_head(int32_t v) { return v < 0; }
+__device__ __forceinline__ int csc_path(int32_t v) { return v & 0x7fffffff; }
+__device__ __forceinline__ bool csc_head(uint16_t v) { return (v & 0x8000u) != 0; }
+__device__ __forceinline__ int csc_path(uint16_t v) { return v & 0x7fff; }
+
 // Segmented sums over the CSC entries of the non-empty links owned by this workgroup (ranks k0..):
 // acc[k - k0] += sum of vals[path] over the entries of link nzlink[k].  Each wavefront walks its
 // contiguous part wt = {first entry, end, rank of the link holding the first entry} of the
 // workgroup's entries in coalesced rows of 64; runs of equal link in a row are reduced by a
 // segmented scan and their tail lane adds one partial into the LDS accumulator.
-template <class T>
-__device__ __forceinline__ void seg_rows_sum(const Prob &p, const T *vals, int k0, int4 wt, double *acc) {
+template <class I, class T>
+__device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0, int4 wt, double *acc) {
   const int lane = threadIdx.x & 63;
   const int ja = wt.x, jb = wt.y;
   if (ja >= jb) return;
   int kbase = wt.z;
   constexpr int U = 4;  // rows whose loads are issued together
   for (int j = ja; j < jb; j += 64 * U) {
-    int32_t v[U];
+    I v[U];
     double val[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int jj = j + 64 * u + lane;
-      v[u] = jj < jb ? p.lpf[jj] : 0;
+      v[u] = jj < jb ? lpf[jj] : (I)0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int jj = j + 64 * u + lane;
-      val[u] = jj < jb ? (double)vals[v[u] & 0x7fffffff] : 0.0;
+      val[u] = jj < jb ? (double)vals[csc_path(v[u])] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int jj = j + 64 * u + lane;
       const bool valid = jj < jb;
-      const bool head = valid && v[u] < 0 && jj != ja;
+      const bool head = valid && csc_head(v[u]) && jj != ja;
       const uint64_t hm = __ballot(head);
       const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
       // segment key: rank of the entry's link; lanes past the end get -3 (after every valid lane)
@@ -296,7 +303,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     }
   }
   __syncthreads();
-  seg_rows_sum(p, s.xf, k0, wt, acc);
+  seg_rows_sum(p.lpf, s.xf, k0, wt, acc);
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -596,7 +603,8 @@ __global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double 
 // ------------------------------------------------------------------------------------------
 // Workgroup engine: the whole solve of one instance inside one workgroup, state in LDS.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *descs, Pools pools,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pools pools,
                                                                const Params *prmp, int project, float *x_out,
                                                                float *S_out, BatchOut *outs) {
   const Params &prm = *prmp;
@@ -614,18 +622,24 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   double *x = S + D;                                 // P
   double *uneg = x + P;                              // P
   double *Dn = uneg + P;                             // D
-  int32_t *pptr = (int32_t *)(Dn + D);               // P + 1
-  int32_t *plinks = pptr + P + 1;                    // nnz
-  int32_t *dptr = plinks + nnz;                      // D + 1
-  int32_t *lptr = dptr + D + 1;                      // E + 1
-  int32_t *lpaths = lptr + E + 1;                    // nnz
-  const int tid = threadIdx.x, nth = blockDim.x;
+  // 16-bit indices (the host admits only instances with P < 2^15 and nnz, E, D < 2^16 here)
+  uint16_t *pptr = (uint16_t *)(Dn + D);             // P + 1
+  uint16_t *plinks = pptr + P + 1;                   // nnz
+  uint16_t *dptr = plinks + nnz;                     // D + 1
+  uint16_t *lptr = dptr + D + 1;                     // E + 1
+  uint16_t *lpf = lptr + E + 1;                      // nnz: CSC path ids, bit 15 on a link's first entry
+  uint16_t *nzl = lpf + nnz;                         // non-empty links in order
+  const int tid = threadIdx.x, nth = NT;
   const int32_t *gi = pools.i32;
-  for (int i = tid; i <= P; i += nth) pptr[i] = gi[d.off_pptr + i];
-  for (int i = tid; i < nnz; i += nth) plinks[i] = gi[d.off_plinks + i];
-  for (int i = tid; i <= D; i += nth) dptr[i] = gi[d.off_dptr + i];
-  for (int i = tid; i <= E; i += nth) lptr[i] = gi[d.off_lptr + i];
-  for (int i = tid; i < nnz; i += nth) lpaths[i] = gi[d.off_lpaths + i];
+  for (int i = tid; i <= P; i += nth) pptr[i] = (uint16_t)gi[d.off_pptr + i];
+  for (int i = tid; i < nnz; i += nth) plinks[i] = (uint16_t)gi[d.off_plinks + i];
+  for (int i = tid; i <= D; i += nth) dptr[i] = (uint16_t)gi[d.off_dptr + i];
+  for (int i = tid; i <= E; i += nth) lptr[i] = (uint16_t)gi[d.off_lptr + i];
+  for (int i = tid; i < nnz; i += nth) {
+    const int32_t v = gi[d.off_lpf + i];
+    lpf[i] = (uint16_t)((v & 0x7fff) | (v < 0 ? 0x8000 : 0));
+  }
+  for (int i = tid; i < d.nzl; i += nth) nzl[i] = (uint16_t)gi[d.off_nzl + i];
   for (int i = tid; i < E; i += nth) {
     Cn[i] = pools.Cn[d.off_E + i];
     gq[i] = make_double2(0.0, 0.0);
@@ -651,8 +665,27 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
   const int lane = tid & (G - 1);
   const int groups = nth >> logG;
   const int w = tid >> 6, l64 = tid & 63, nw = nth >> 6;
+  // this wavefront's part of the CSC entries for the link step, and the rank (among non-empty
+  // links) of the link holding its first entry
+  int4 bwt;
+  {
+    const int per = (nnz + nw - 1) / nw;
+    const int ja = min(nnz, w * per), jb = min(nnz, (w + 1) * per);
+    int lo = 0, hi = E - 1;  // last link e with lptr[e] <= ja: the non-empty link holding entry ja
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if ((int)lptr[mid] <= ja) lo = mid; else hi = mid - 1;
+    }
+    int a = 0, b = d.nzl;  // its rank: first position in nzl not below lo
+    while (a < b) {
+      const int mid = (a + b) >> 1;
+      if ((int)nzl[mid] < lo) a = mid + 1; else b = mid;
+    }
+    bwt = make_int4(ja, jb, a, 0);
+  }
   while (!cs.stop) {
     const double inv_f = cs.inv_f;
+    for (int k = tid; k < d.nzl; k += nth) Lx[k] = 0.0;  // link-load accumulators, by rank
     Dem dm;
     dm.alpha = cs.alpha;
     dm.binv = 1.0 / cs.beta;
@@ -709,21 +742,20 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
       }
     }
     __syncthreads();
-    // link step
-    for (int e = w; e < E; e += nw) {
-      const int j0 = lptr[e], j1 = lptr[e + 1];
-      double acc = 0.0;
-      for (int j = j0 + l64; j < j1; j += 64) acc += x[lpaths[j]];
-      acc = wave_sum_d(acc);
-      if (l64 == 0 && j1 > j0) {
-        const double2 v = gq[e];
-        const double gold = v.x * inv_f;
-        const int ne = j1 - j0;
-        const double gn = fmax(gold + (acc - Cn[e]) / (double)(1 + ne), 0.0);
-        gq[e] = make_double2(gn, gold - gn);
-        dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
-        cap_v = fmax(cap_v, (acc - Cn[e]) / Cn[e]);
-      }
+    // link step: loads by segmented sums over the CSC rows (each wavefront a contiguous part),
+    // then one thread per non-empty link
+    seg_rows_sum(lpf, x, 0, bwt, Lx);
+    __syncthreads();
+    for (int k = tid; k < d.nzl; k += nth) {
+      const int e = nzl[k];
+      const double load = Lx[k];
+      const int ne = lptr[e + 1] - lptr[e];
+      const double2 v = gq[e];
+      const double gold = v.x * inv_f;
+      const double gn = fmax(gold + (load - Cn[e]) / (double)(1 + ne), 0.0);
+      gq[e] = make_double2(gn, gold - gn);
+      dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
+      cap_v = fmax(cap_v, (load - Cn[e]) / Cn[e]);
     }
     // partial sums and decision
     ds2 = wave_sum_d(ds2);
@@ -764,7 +796,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
     for (int pass = 0; pass < 2; ++pass) {
       for (int e = w; e < E; e += nw) {
         double acc = 0.0;
-        for (int j = lptr[e] + l64; j < lptr[e + 1]; j += 64) acc += x[lpaths[j]];
+        for (int j = lptr[e] + l64; j < lptr[e + 1]; j += 64) acc += x[csc_path(lpf[j])];
         acc = wave_sum_d(acc);
         if (l64 == 0) Lx[e] = acc;
       }
@@ -804,11 +836,11 @@ __global__ __launch_bounds__(kBlockThreads) void k_block_solve(const BatchDesc *
       if (!(V > 0.0)) continue;
       const int j0 = lptr[e], j1 = lptr[e + 1];
       for (int j = j0 + l64; j < j1; j += 64) {
-        const int r = lpaths[j];
+        const int r = csc_path(lpf[j]);
         const uint64_t kr = trim_key((float)uneg[r], r);
         double before = 0.0;
         for (int i = j0; i < j1; ++i) {
-          const int q = lpaths[i];
+          const int q = csc_path(lpf[i]);
           if (trim_key((float)uneg[q], q) > kr) before += x[q];
         }
         const double dd = fmin(x[r], fmax(V - before, 0.0));
@@ -938,7 +970,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_adj_link(Prob p, FwdState fout
   const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   __syncthreads();
-  seg_rows_sum(p, a.ab, k0, wt, acc);
+  seg_rows_sum(p.lpf, a.ab, k0, wt, acc);
   __syncthreads();
   for (int k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
     const int e = p.nzlink[k];
@@ -1060,19 +1092,35 @@ hipError_t launch_project(const Prob &p, const State &s, const ProjBuf &b, float
   return hipGetLastError();
 }
 
-hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
-                              float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_block_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+template <int NT>
+hipError_t launch_block_nt(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
+                           float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, hipStream_t st) {
+  hipError_t e = hipFuncSetAttribute((const void *)k_block_solve<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_solve, dim3(n), dim3(kBlockThreads), lds_bytes, st, descs, pools, prm, project, x_out,
-                     S_out, outs);
+  hipLaunchKernelGGL(k_block_solve<NT>, dim3(n), dim3(NT), lds_bytes, st, descs, pools, prm, project, x_out, S_out,
+                     outs);
   return hipGetLastError();
 }
 
+// threads: 256, 512 or 1024 per workgroup (one instance per workgroup)
+hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
+                              float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, int threads,
+                              hipStream_t st) {
+  switch (threads) {
+    case 256: return launch_block_nt<256>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 512: return launch_block_nt<512>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 1024: return launch_block_nt<1024>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Dynamic LDS of the workgroup engine for one instance; SIZE_MAX when its indices do not fit the
+// 16-bit LDS encoding (P < 2^15 for the head bit, nnz, E, D < 2^16).
 size_t block_lds_bytes(int E, int P, int D, int nnz) {
+  if (P >= 32768 || nnz >= 65536 || E >= 65536 || D >= 65536) return SIZE_MAX;
   return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 8) + (size_t)P * 8 * 2 +
-         (size_t)4 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz) + 16;
+         (size_t)2 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz + E) + 16;
 }
 
 }  // namespace te

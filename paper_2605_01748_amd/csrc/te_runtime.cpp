@@ -25,7 +25,7 @@ hipError_t launch_link_timed(const Prob &, const State &, const Params *, int, h
 hipError_t launch_finish(const State &, const Params *, int, hipStream_t);
 hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *, float *, double, int, hipStream_t);
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
-                              BatchOut *, size_t, hipStream_t);
+                              BatchOut *, size_t, int, hipStream_t);
 size_t block_lds_bytes(int E, int P, int D, int nnz);
 hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStream_t);
 hipError_t launch_adj_iteration(const Prob &, int, int, const FwdState &, const FwdState &, const AdjState &, double,
@@ -128,6 +128,7 @@ struct te_batch {
   int64_t totP = 0, totD = 0;
   std::vector<double> scales;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int32_t tuned_threads = 0;  // workgroup size picked on the first solve with block_threads = 0
 };
 
 extern "C" {
@@ -227,7 +228,9 @@ te_status upload_values(te_ctx *c) {
   d.off_plinks = (int64_t)c->P + 1;
   d.off_dptr = d.off_plinks + c->nnz;
   d.off_lptr = d.off_dptr + c->D + 1;
-  d.off_lpaths = d.off_lptr + c->E + 1;
+  d.off_lpf = d.off_lptr + c->E + 1 + c->nnz;  // the pool holds lpaths, then lpf
+  d.off_nzl = d.off_lpf + c->nnz;
+  d.nzl = (int32_t)c->nzlink.size();
   d.off_E = d.off_P = d.off_D = 0;
   d.scale = c->scale;
   HIPCHK(hipMemcpy(c->d_desc, &d, sizeof(d), hipMemcpyHostToDevice));
@@ -278,6 +281,8 @@ te_status check_options(const te_options *o) {
     return fail(TE_ERR_INVALID, "invalid options (gamma, beta0, A, C, beta bounds or alpha_target)");
   if (o->fixed_iters <= 0 && o->max_iters <= 0) return fail(TE_ERR_INVALID, "max_iters must be > 0");
   if (o->sched_len < 0) return fail(TE_ERR_INVALID, "sched_len < 0");
+  if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512 && o->block_threads != 1024)
+    return fail(TE_ERR_INVALID, "block_threads must be 0, 256, 512 or 1024");
   return TE_OK;
 }
 
@@ -331,11 +336,12 @@ hipError_t copy_fwd(const FwdState &dst, const FwdState &src, const te_ctx *c, h
   return e;
 }
 
-void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms) {
+void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms, int block_threads) {
   s->iters = c.k;
   s->flags = c.flags;
   s->stop_iter = c.stop_iter;
   s->engine = engine;
+  s->block_threads = engine == TE_ENGINE_BLOCK ? block_threads : 0;
   s->final_alpha = c.alpha;
   s->beta = c.beta;
   s->r = c.r;
@@ -554,7 +560,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   if (engine == TE_ENGINE_BLOCK) {
     Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev};
     HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
-                              c->lds_bytes, stream));
+                              c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads, stream));
   } else {
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
@@ -634,7 +640,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    fill_stats(stats, fin, engine, ms);
+    fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads);
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
@@ -836,8 +842,11 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
     pool.insert(pool.end(), c->dptr.begin(), c->dptr.end());
     d.off_lptr = (int64_t)pool.size();
     pool.insert(pool.end(), c->lptr.begin(), c->lptr.end());
-    d.off_lpaths = (int64_t)pool.size();
-    pool.insert(pool.end(), c->lpaths.begin(), c->lpaths.end());
+    d.off_lpf = (int64_t)pool.size();
+    pool.insert(pool.end(), c->lpf.begin(), c->lpf.end());
+    d.off_nzl = (int64_t)pool.size();
+    pool.insert(pool.end(), c->nzlink.begin(), c->nzlink.end());
+    d.nzl = (int32_t)c->nzlink.size();
     d.off_E = offE;
     d.off_P = offP;
     d.off_D = offD;
@@ -884,12 +893,43 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
   if (s != TE_OK) return s;
   hipStream_t stream = (hipStream_t)hip_stream;
   HIPCHK(hipSetDevice(b->device));
+  Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
+  int threads = o.block_threads;
+  if (threads == 0) {
+    if (b->tuned_threads == 0) {
+      // workgroup-size tuning on the first solve: 16 iterations of the batch with each candidate,
+      // timed with events; the fastest is kept (the outputs are overwritten by the solve below)
+      te_options t;
+      te_default_options(&t);
+      t.fixed_iters = 16;
+      t.project = 0;
+      const int cand[3] = {1024, 512, 256};
+      float best = 0.f;
+      for (int i = 0; i < 3; ++i) {
+        s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
+        if (s != TE_OK) return s;
+        for (int rep = 0; rep < 2; ++rep) {  // the first launch also sets up the kernel
+          HIPCHK(hipEventRecord(b->ev0, stream));
+          HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev, b->d_out,
+                                    b->lds_bytes, cand[i], stream));
+          HIPCHK(hipEventRecord(b->ev1, stream));
+        }
+        HIPCHK(hipEventSynchronize(b->ev1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        if (b->tuned_threads == 0 || ms < best) {
+          best = ms;
+          b->tuned_threads = cand[i];
+        }
+      }
+    }
+    threads = b->tuned_threads;
+  }
   s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   HIPCHK(hipEventRecord(b->ev0, stream));
-  Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
   HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, o.project, x_out_dev, S_out_dev, b->d_out,
-                            b->lds_bytes, stream));
+                            b->lds_bytes, threads, stream));
   HIPCHK(hipEventRecord(b->ev1, stream));
   if (stats) {
     HIPCHK(hipStreamSynchronize(stream));
@@ -908,7 +948,7 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
       fin.s = outs[k].s;
       fin.cap_viol = outs[k].cap_viol;
       fin.dem_viol = outs[k].dem_viol;
-      fill_stats(&stats[k], fin, TE_ENGINE_BLOCK, ms);
+      fill_stats(&stats[k], fin, TE_ENGINE_BLOCK, ms, threads);
     }
   }
   return TE_OK;

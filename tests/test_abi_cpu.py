@@ -80,3 +80,28 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(te.TEError) as ex:
         te.Problem(_inst())
     assert ex.value.status == te.TE_ERR_DEVICE
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of te_options and te_stats have the header's field offsets and sizes
+    (checked by compiling the header with the host compiler)."""
+    import ctypes
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    fields = {"te_options": te._Options, "te_stats": te._Stats}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "te.h"', "int main(void) {"]
+    for name, cls in fields.items():
+        src.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            src.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(c), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.splitlines())
+    for name, cls in fields.items():
+        assert int(out[f"{name} size"]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)

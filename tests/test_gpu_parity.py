@@ -223,19 +223,53 @@ def test_adaptive_solve_reaches_maxmin_config1(te, c1):
     assert opt >= 0.99
 
 
-def test_batch_equals_individual(te):
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batch_equals_individual(te, threads):
+    """One launch over uneven instances gives each the same rates as its own workgroup-engine solve
+    with the same workgroup size (bit for bit)."""
     scen = W.config4_scenarios(0, n_scen=24)
     probs = [te.Problem(s) for s in scen]
     batch = te.Batch(probs)
-    opts = te.Options(fixed_iters=200)
+    opts = te.Options(fixed_iters=200, block_threads=threads)
     xb, Sb, stb = batch.solve(opts)
     xb = xb.cpu().numpy()
     off = 0
     for p, s, stt in zip(probs, scen, stb):
-        x, S, st = p.solve(te.Options(fixed_iters=200, engine=te.ENGINE_BLOCK))
+        x, S, st = p.solve(te.Options(fixed_iters=200, engine=te.ENGINE_BLOCK, block_threads=threads))
         np.testing.assert_array_equal(xb[off:off + s.n_paths], x.cpu().numpy())
         assert stt["iters"] == st["iters"] == 200
+        assert stt["block_threads"] == st["block_threads"] == threads
         off += s.n_paths
+
+
+@pytest.mark.parametrize("threads", [256, 512])
+def test_parity_block_workgroup_sizes(te, c1, threads):
+    """The workgroup engine at every workgroup size against the oracle (schedule replayed)."""
+    K = 256
+    r, sb, sa = _oracle_run(c1, K)
+    prob = te.Problem(c1)
+    opts = te.Options(fixed_iters=K, project=False, engine=te.ENGINE_BLOCK, block_threads=threads,
+                      sched_beta=sb, sched_alpha=sa)
+    x, S, st = prob.solve(opts)
+    assert st["block_threads"] == threads
+    err = _report(f"config1 block threads={threads}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
+                  c1.demand)
+    assert err.max() <= REL
+
+
+def test_batch_tuned_workgroup_size(te):
+    """block_threads = 0 on a batch: the size measured fastest on the first solve is kept, and the
+    result equals the forced solve at that size."""
+    scen = W.config4_scenarios(1, n_scen=64)
+    batch = te.Batch([te.Problem(s) for s in scen])
+    x1, _, st1 = batch.solve(te.Options(fixed_iters=64))
+    t = st1[0]["block_threads"]
+    assert t in (256, 512, 1024) and all(s["block_threads"] == t for s in st1)
+    x2, _, st2 = batch.solve(te.Options(fixed_iters=64))
+    assert st2[0]["block_threads"] == t
+    x3, _, _ = batch.solve(te.Options(fixed_iters=64, block_threads=t))
+    np.testing.assert_array_equal(x1.cpu().numpy(), x3.cpu().numpy())
+    print(f"tuned workgroup size for 64 scenarios: {t}")
 
 
 def test_update_and_warm_start(te, c1, torch):
