@@ -43,6 +43,13 @@ def log(*a):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_demand_k_link_150node_traffic.md")
 
 
+def optimality(S, opt, theta):
+    """The paper's optimality metric (section 4.1): mean over demands of min(S_d / max(OPT_d, theta), 1)."""
+    S = np.asarray(S, np.float64)
+    opt = np.asarray(opt, np.float64)
+    return float(np.mean(np.minimum(S / np.maximum(opt, theta), 1.0)))
+
+
 def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
@@ -106,12 +113,11 @@ def profile_run(args, torch, te, W, dev):
     log(f"iters {args.iters}: {st['ms']:.3f} ms")
 
 
-def large_run(args, torch, te, W, O, dev):
+def large_run(args, torch, te, W, dev):
     """The 1,000-node two-level WAN (50 regions x 20 nodes + backbone, all ~1M ordered pairs, k = 4):
     the size at which the per-iteration kernels move enough bytes for the HBM roofline to matter.
-    Reports mean kernel durations over 32 iterations, the roofline of both kernels, ms per
-    iteration of a plain 64-iteration solve, and the error against the FP64 oracle after 16
-    iterations with the oracle's schedule replayed (all demands)."""
+    Reports mean kernel durations over 32 iterations, the roofline of both kernels and ms per
+    iteration of a plain 64-iteration solve (its parity with the oracle is a GPU test)."""
     t0 = time.time()
     last = [0.0]
 
@@ -138,20 +144,10 @@ def large_run(args, torch, te, W, O, dev):
     prob.solve(o64, stats=False)
     torch.cuda.synchronize()
     ms_iter = (time.perf_counter() - t1) * 1e3 / 64
-    K = 16
-    t2 = time.perf_counter()
-    r = O.solve(inst, O.Options(fixed_iters=K, project=False), want_state=False)
-    t_orc = time.perf_counter() - t2
-    sb, sa = r.schedule
-    _, S, _ = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, sched_beta=sb, sched_alpha=sa))
-    S = S.cpu().numpy().astype(np.float64)
-    orc = r.S_raw * r.scale
-    err = np.abs(S - orc) / np.maximum(np.abs(orc), 1e-2 * inst.demand.max())
     out = {"workload": "two-level WAN: 50 Waxman regions x 20 nodes + backbone over 4 gateways/region, "
                        "all ordered pairs, 1+Pareto(1.2) gravity weights, k=4 latency-shortest paths",
            "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
-           "ms_per_iteration": round(ms_iter, 4), "roofline": rl,
-           "parity_K16_max_rel_err": float(f"{err.max():.3e}"), "oracle_K16_s": round(t_orc, 2)}
+           "ms_per_iteration": round(ms_iter, 4), "roofline": rl}
     print(json.dumps(out), flush=True)
 
 
@@ -175,7 +171,6 @@ def main():
         sys.exit(2)
 
     import torch
-    import oracle as O
     import paper_2605_01748_amd as te
     import workloads as W
 
@@ -188,7 +183,7 @@ def main():
         profile_run(args, torch, te, W, dev)
         return
     if args.large:
-        large_run(args, torch, te, W, O, dev)
+        large_run(args, torch, te, W, dev)
         return
 
     t0 = time.time()
@@ -204,15 +199,15 @@ def main():
         x, S, st = prob.solve(te.Options(fixed_iters=K, project=project, engine=te.ENGINE_GRAPH, **kw))
         return x, S, st
 
-    def optimality(S):
-        return O.optimality(S.cpu().numpy().astype(np.float64), opt_S, THETA * scale)
+    def opt_of(S):
+        return optimality(S.cpu().numpy(), opt_S, THETA * scale)
 
     # ---- K*: smallest budget on a geometric grid (ratio 2^(1/4)) reaching >= 0.99 ----
     grid = sorted({int(round(32 * 2 ** (i / 4))) for i in range(0, 44)})
     K_star, opt_at = None, None
     for K in grid:
         _, S, st = run(K)
-        o = optimality(S)
+        o = opt_of(S)
         log(f"  K={K:6d} optimality {o:.5f} alpha {st['final_alpha']:.0f} beta {st['beta']:.4g}")
         if o >= 0.99:
             K_star, opt_at = K, o
@@ -256,6 +251,7 @@ def main():
     orc_S = None
     cpu = None
     if not args.no_cpu_baseline:
+        import oracle as O  # the CPU baseline: the FP64 oracle timed on the host
         threads = os.cpu_count() or 1
         os.environ.setdefault("OMP_NUM_THREADS", str(threads))
         # bounded sample: whole oracle solves at K* until at least 10 s of wall time have passed
@@ -277,7 +273,7 @@ def main():
                "kind": "oracle",
                "sample": f"{n_orc} full FP64 oracle solves of the same instance at K*={K_star} iterations "
                          f"(OpenMP, {os.environ.get('OMP_NUM_THREADS')} threads); mean ms per solve",
-               "oracle_optimality": round(O.optimality(r.S, opt_S, THETA * scale), 5),
+               "oracle_optimality": round(optimality(r.S, opt_S, THETA * scale), 5),
                "gpu_vs_oracle_max_rel_err": float(f"{err.max():.3e}")}
         log(f"oracle: {t_orc * 1e3:.1f} ms, GPU-vs-oracle max rel err {err.max():.3e}")
 
@@ -291,7 +287,7 @@ def main():
         K1 = None
         for K in grid:
             _, S, _ = p1.solve(te.Options(fixed_iters=K, engine=te.ENGINE_BLOCK))
-            if O.optimality(S.cpu().numpy().astype(np.float64), g1, THETA * 100.0) >= 0.99:
+            if optimality(S.cpu().numpy(), g1, THETA * 100.0) >= 0.99:
                 K1 = K
                 break
         scen = W.config4_scenarios(0, n_scen=args.n_scen)

@@ -95,6 +95,12 @@ typedef struct {
   int32_t block_threads; /* workgroup engine: threads per workgroup, 256, 512 or 1024; 0 (default):
                             1024 for single solves, and for batches the fastest of the three measured
                             on the batch's first solve (kept by the batch handle) */
+  int32_t warm;        /* 1: continue from the state the handle's last graph-engine solve left (rates,
+                          every dual, beta and alpha; alpha capped at alpha_target) instead of
+                          initialising, e.g. after te_update; the iteration count restarts at 0.
+                          Uses the graph engine; TE_ERR_STATE if there is no such state (none yet,
+                          or te_grad / te_kernel_times ran since).  If te_update changed the unit
+                          scale, the state is converted to the new units. */
   /* Optional replay of a (beta_k, alpha_k) schedule, host arrays of sched_len entries: iteration k
    * uses beta = sched_beta[k], alpha = sched_alpha[k] (the last entry repeats), no adaptation. */
   const double *sched_beta;

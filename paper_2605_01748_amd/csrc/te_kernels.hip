@@ -129,6 +129,42 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, dou
   }
 }
 
+// Continuation from the state of the previous solve (warm restart): rate-like state converted to
+// the current units (rescale = old scale / new scale), the control record restarted at iteration 0
+// with the previous beta and alpha (alpha capped at the target; a replayed schedule overrides both).
+__global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
+  const Params &prm = *prmp;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  if (rescale != 1.0) {
+    for (int r = tid; r < p.P; r += nth) {
+      const double v = s.x[r] * rescale;
+      s.x[r] = v;
+      s.xf[r] = (float)v;
+      s.uneg[r] *= rescale;
+    }
+    for (int c = tid; c < p.D; c += nth) {
+      s.udem[c] *= rescale;
+      s.S[c] *= rescale;
+    }
+    for (int e = tid; e < p.E; e += nth) {
+      const double2 v = s.gq[e];
+      s.gq[e] = make_double2(v.x * rescale, v.y * rescale);
+    }
+  }
+  if (tid == 0) {
+    const Ctrl fin = s.ctrl[2];
+    Ctrl c = initial_ctrl(prm);
+    if (prm.sched_beta == nullptr) {
+      c.beta = fin.beta;
+      c.alpha = fmin(fin.alpha, prm.alpha_target);
+    }
+    s.ctrl[0] = c;
+    s.ctrl[1] = c;
+    s.ctrl[2] = c;
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Step a1 + a2: gather along paths, per-demand Newton-bisection, rate and dual updates.
 // ------------------------------------------------------------------------------------------
@@ -1046,6 +1082,15 @@ hipError_t launch_init(const Prob &p, const State &s, const Params *prm, const f
   if (blocks > 2048) blocks = 2048;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, st, p, s, prm, x0, inv_scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_warm(const Prob &p, const State &s, const Params *prm, double rescale, hipStream_t st) {
+  int n = p.P > p.E ? p.P : p.E;
+  int blocks = (n + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_warm, dim3(blocks), dim3(256), 0, st, p, s, prm, rescale);
   return hipGetLastError();
 }
 

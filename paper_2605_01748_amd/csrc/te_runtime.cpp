@@ -19,6 +19,7 @@
 
 namespace te {
 hipError_t launch_init(const Prob &, const State &, const Params *, const float *, double, hipStream_t);
+hipError_t launch_warm(const Prob &, const State &, const Params *, double, hipStream_t);
 hipError_t launch_iteration(const Prob &, const State &, const Params *, int, hipStream_t);
 hipError_t launch_demand_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
 hipError_t launch_link_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
@@ -99,6 +100,7 @@ struct te_ctx {
   size_t lds_bytes = 0;
   // recorded solve for te_grad
   int32_t rec_K = 0, rec_ck = 16, rec_warm = 0;
+  double state_scale = 0.0;  // unit scale of the state the last graph-engine solve left (0: none)
   double *d_log = nullptr;      // [2 * log_cap]: beta log then alpha log
   int32_t log_cap = 0;
   float *d_x0rec = nullptr;     // warm start of the recorded solve (caller units), if any
@@ -551,6 +553,12 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     if (o.fixed_iters <= 0) return fail(TE_ERR_INVALID, "record = 1 needs fixed_iters > 0");
     engine = TE_ENGINE_GRAPH;
   }
+  if (o.warm) {
+    if (c->state_scale <= 0.0) return fail(TE_ERR_STATE, "warm = 1 needs an earlier graph-engine solve on this handle");
+    if (o.record) return fail(TE_ERR_INVALID, "warm = 1 cannot be recorded for te_grad (the gradient starts cold)");
+    if (engine == TE_ENGINE_BLOCK) return fail(TE_ERR_INVALID, "warm = 1 runs on the graph engine");
+    engine = TE_ENGINE_GRAPH;
+  }
   if (engine == TE_ENGINE_AUTO) engine = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   if (engine == TE_ENGINE_BLOCK && c->lds_bytes > kMaxBlockLds)
     return fail(TE_ERR_INVALID, "instance needs %zu bytes of LDS, more than one workgroup has", c->lds_bytes);
@@ -564,7 +572,11 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   } else {
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
-    HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, 1.0 / c->scale, stream));
+    if (o.warm)
+      HIPCHK(launch_warm(c->prob, c->st, c->d_params, c->state_scale / c->scale, stream));
+    else
+      HIPCHK(launch_init(c->prob, c->st, c->d_params, x0_dev, 1.0 / c->scale, stream));
+    c->state_scale = c->scale;
     int launched = 0;
     if (o.record) {
       // plain launches with the (beta, alpha) log; the gradient pass replays it
@@ -666,6 +678,7 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
         if (f) (void)hipEventDestroy(f);
       return fail(TE_ERR_DEVICE, "event creation failed");
     }
+  c->state_scale = 0.0;  // this run overwrites the state a warm restart would continue from
   hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, 1.0 / c->scale, stream);
   for (int k = 0; k < iters && err == hipSuccess; ++k) {
     err = launch_demand_timed(c->prob, c->st, c->d_params, k & 1, stream, ev[4 * k], ev[4 * k + 1]);
@@ -742,6 +755,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
   const FwdState work = fwd_of(c->st);
   // forward pass with checkpoints every ck iterations (state + the control record read by the next iteration)
+  c->state_scale = 0.0;  // the replay below overwrites the state a warm restart would continue from
   HIPCHK(launch_init(c->prob, c->st, c->d_params, c->rec_warm ? c->d_x0rec : nullptr, 1.0 / c->scale,
                      stream));
   for (int k = 0; k < K; ++k) {
