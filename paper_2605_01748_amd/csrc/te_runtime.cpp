@@ -79,6 +79,7 @@ struct te_ctx {
   // device
   Prob prob{};
   State st{};
+  FwdState work{};  // the iteration state block; st.x, st.uneg, st.udem, st.S and st.gq point into it
   ProjBuf pb{};
   Params *d_params = nullptr;
   Params *h_params = nullptr;  // pinned staging
@@ -92,8 +93,10 @@ struct te_ctx {
   // workgroup engine (single instance)
   BatchDesc *d_desc = nullptr;
   BatchOut *d_bout = nullptr;
-  // graph of kChunk iterations
+  // graph of kChunk iterations, and the same with the (beta, alpha) log of a recorded solve
   hipGraphExec_t chunk = nullptr;
+  hipGraphExec_t rec_chunk = nullptr;
+  double *rec_chunk_log = nullptr;
   int32_t *h_flag = nullptr;  // pinned: stop flags of chunks in flight
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing
   hipEvent_t pe[2] = {nullptr, nullptr};    // polling of the stop flag
@@ -103,7 +106,6 @@ struct te_ctx {
   double state_scale = 0.0;  // unit scale of the state the last graph-engine solve left (0: none)
   double *d_log = nullptr;      // [2 * log_cap]: beta log then alpha log
   int32_t log_cap = 0;
-  float *d_x0rec = nullptr;     // warm start of the recorded solve (caller units), if any
   std::vector<FwdState> ckpt;   // checkpoints every rec_ck iterations
   std::vector<Ctrl *> ckpt_ctrl;
   std::vector<FwdState> seg;    // one segment of recomputed states
@@ -288,13 +290,14 @@ te_status check_options(const te_options *o) {
   return TE_OK;
 }
 
-te_status build_chunk_graph(te_ctx *c, hipStream_t stream) {
-  if (c->chunk) return TE_OK;
+// Captures kChunk iterations on state st into *out (once; kept until the handle is destroyed).
+te_status capture_chunk(te_ctx *c, const State &st, hipGraphExec_t *out) {
+  if (*out) return TE_OK;
   hipStream_t cap;
   HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
   for (int i = 0; i < kChunk; ++i) {
-    hipError_t e = launch_iteration(c->prob, c->st, c->d_params, i & 1, cap);
+    hipError_t e = launch_iteration(c->prob, st, c->d_params, i & 1, cap);
     if (e != hipSuccess) {
       hipGraph_t g;
       (void)hipStreamEndCapture(cap, &g);
@@ -304,38 +307,57 @@ te_status build_chunk_graph(te_ctx *c, hipStream_t stream) {
   }
   hipGraph_t g;
   HIPCHK(hipStreamEndCapture(cap, &g));
-  HIPCHK(hipGraphInstantiate(&c->chunk, g, nullptr, nullptr, 0));
+  HIPCHK(hipGraphInstantiate(out, g, nullptr, nullptr, 0));
   HIPCHK(hipGraphDestroy(g));
   HIPCHK(hipStreamDestroy(cap));
-  (void)stream;
   return TE_OK;
 }
 
+te_status build_chunk_graph(te_ctx *c, hipStream_t) { return capture_chunk(c, c->st, &c->chunk); }
+
+// An iteration state (x, u_neg, u_dem, S, (g, q)) lives in one block, x | u_neg | u_dem | S | gq,
+// so that a checkpoint or a segment step is one copy.
+size_t fwd_doubles(const te_ctx *c) { return 2 * (size_t)c->P + 2 * (size_t)c->D + 2 * (size_t)c->E; }
+
+FwdState fwd_in(double *base, const te_ctx *c) {
+  FwdState f;
+  f.x = base;
+  f.uneg = f.x + c->P;
+  f.udem = f.uneg + c->P;
+  f.S = f.udem + c->D;
+  f.gq = reinterpret_cast<double2 *>(f.S + c->D);  // offset 2(P + D) doubles: 16-byte aligned
+  return f;
+}
+
 hipError_t alloc_fwd(FwdState &f, const te_ctx *c) {
-  hipError_t e = dalloc(&f.x, c->P);
-  if (e == hipSuccess) e = dalloc(&f.uneg, c->P);
-  if (e == hipSuccess) e = dalloc(&f.udem, c->D);
-  if (e == hipSuccess) e = dalloc(&f.S, c->D);
-  if (e == hipSuccess) e = dalloc(&f.gq, c->E);
+  double *base = nullptr;
+  hipError_t e = dalloc(&base, fwd_doubles(c));
+  if (e == hipSuccess) f = fwd_in(base, c);
   return e;
 }
 
 void free_fwd(FwdState &f) {
-  void *b[] = {f.x, f.uneg, f.udem, f.S, f.gq};
-  for (void *p : b)
-    if (p) (void)hipFree(p);
+  if (f.x) (void)hipFree(f.x);
   f = FwdState{};
 }
 
-FwdState fwd_of(const State &s) { return FwdState{s.x, s.uneg, s.udem, s.S, s.gq}; }
+te_status ensure_ckpts(te_ctx *c, int n) {
+  while ((int)c->ckpt.size() < n) {
+    FwdState f{};
+    Ctrl *cc = nullptr;
+    if (alloc_fwd(f, c) != hipSuccess || dalloc(&cc, 1) != hipSuccess) {
+      free_fwd(f);
+      if (cc) (void)hipFree(cc);
+      return fail(TE_ERR_OOM, "checkpoint allocation failed");
+    }
+    c->ckpt.push_back(f);
+    c->ckpt_ctrl.push_back(cc);
+  }
+  return TE_OK;
+}
 
 hipError_t copy_fwd(const FwdState &dst, const FwdState &src, const te_ctx *c, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(dst.x, src.x, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst.uneg, src.uneg, sizeof(double) * c->P, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst.udem, src.udem, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst.S, src.S, sizeof(double) * c->D, hipMemcpyDeviceToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(dst.gq, src.gq, sizeof(double2) * c->E, hipMemcpyDeviceToDevice, st);
-  return e;
+  return hipMemcpyAsync(dst.x, src.x, sizeof(double) * fwd_doubles(c), hipMemcpyDeviceToDevice, st);
 }
 
 void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms, int block_threads) {
@@ -453,9 +475,8 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
                     c->nzptr.size() + c->blk.size();
   const int nA = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
-            dalloc(&c->d_Cn, c->E) == hipSuccess && dalloc(&c->st.x, c->P) == hipSuccess && dalloc(&c->st.xf, c->P) == hipSuccess &&
-            dalloc(&c->st.uneg, c->P) == hipSuccess && dalloc(&c->st.udem, c->D) == hipSuccess &&
-            dalloc(&c->st.S, c->D) == hipSuccess && dalloc(&c->st.gq, c->E) == hipSuccess &&
+            dalloc(&c->d_Cn, c->E) == hipSuccess && alloc_fwd(c->work, c) == hipSuccess &&
+            dalloc(&c->st.xf, c->P) == hipSuccess &&
             dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA * 4) == hipSuccess &&
             dalloc(&c->st.partB, (size_t)2 * nB * 4) == hipSuccess &&
             dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
@@ -464,6 +485,11 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
             dalloc(&c->d_params, 1) == hipSuccess && dalloc(&c->d_desc, 1) == hipSuccess &&
             dalloc(&c->d_bout, 1) == hipSuccess && dalloc(&c->d_wtab, wtab.size()) == hipSuccess;
   if (!ok) return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
+  c->st.x = c->work.x;
+  c->st.uneg = c->work.uneg;
+  c->st.udem = c->work.udem;
+  c->st.S = c->work.S;
+  c->st.gq = c->work.gq;
   if (hipMemcpy(c->d_wtab, wtab.data(), sizeof(int4) * wtab.size(), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the link work table failed"));
   if (hipHostMalloc((void **)&c->h_params, sizeof(Params)) != hipSuccess ||
@@ -590,15 +616,38 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
       sr.log_beta = c->d_log;
       sr.log_alpha = c->d_log + c->log_cap;
       sr.log_cap = c->log_cap;
-      for (launched = 0; launched < o.fixed_iters; ++launched)
-        HIPCHK(launch_iteration(c->prob, sr, c->d_params, launched & 1, stream));
-      c->rec_K = o.fixed_iters;
-      c->rec_ck = o.ckpt_every > 0 ? o.ckpt_every : 16;
-      c->rec_warm = x0_dev != nullptr;
-      if (x0_dev) {
-        if (!c->d_x0rec) HIPCHK(dalloc(&c->d_x0rec, c->P));
-        HIPCHK(hipMemcpyAsync(c->d_x0rec, x0_dev, sizeof(float) * c->P, hipMemcpyDeviceToDevice, stream));
+      // checkpoints for te_grad every ck iterations: the state and the control record the next
+      // iteration reads
+      const int ck = o.ckpt_every > 0 ? o.ckpt_every : 16;
+      s = ensure_ckpts(c, (o.fixed_iters + ck - 1) / ck);
+      if (s != TE_OK) return s;
+      c->rec_K = 0;  // valid again once the recording is complete
+      if (ck % kChunk == 0) {  // the logging iterations as captured chunks (recaptured if the log moved)
+        if (c->rec_chunk && c->rec_chunk_log != c->d_log) {
+          HIPCHK(hipGraphExecDestroy(c->rec_chunk));
+          c->rec_chunk = nullptr;
+        }
+        s = capture_chunk(c, sr, &c->rec_chunk);
+        if (s != TE_OK) return s;
+        c->rec_chunk_log = c->d_log;
       }
+      for (launched = 0; launched < o.fixed_iters;) {
+        if (launched % ck == 0) {
+          HIPCHK(copy_fwd(c->ckpt[launched / ck], c->work, c, stream));
+          HIPCHK(hipMemcpyAsync(c->ckpt_ctrl[launched / ck], c->st.ctrl + ((launched + 1) & 1), sizeof(Ctrl),
+                                hipMemcpyDeviceToDevice, stream));
+        }
+        if (ck % kChunk == 0 && launched + kChunk <= o.fixed_iters) {
+          HIPCHK(hipGraphLaunch(c->rec_chunk, stream));
+          launched += kChunk;
+        } else {
+          HIPCHK(launch_iteration(c->prob, sr, c->d_params, launched & 1, stream));
+          ++launched;
+        }
+      }
+      c->rec_K = o.fixed_iters;
+      c->rec_ck = ck;
+      c->rec_warm = x0_dev != nullptr;  // a given x^0 does not depend on the demands
     } else if (o.fixed_iters > 0) {
       const int K = o.fixed_iters;
       while (launched + kChunk <= K) {
@@ -713,17 +762,8 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   HIPCHK(hipMemcpyAsync(lb.data(), c->d_log, sizeof(double) * K, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipMemcpyAsync(la.data(), c->d_log + c->log_cap, sizeof(double) * K, hipMemcpyDeviceToHost, stream));
   HIPCHK(hipStreamSynchronize(stream));
-  // buffers (kept on the handle)
-  while ((int)c->ckpt.size() < nck) {
-    FwdState f{};
-    Ctrl *cc = nullptr;
-    if (alloc_fwd(f, c) != hipSuccess || dalloc(&cc, 1) != hipSuccess) {
-      free_fwd(f);
-      return fail(TE_ERR_OOM, "checkpoint allocation failed");
-    }
-    c->ckpt.push_back(f);
-    c->ckpt_ctrl.push_back(cc);
-  }
+  // buffers (kept on the handle); the checkpoints were taken by the recorded solve
+  if ((int)c->ckpt.size() < nck) return fail(TE_ERR_STATE, "checkpoints of the recorded solve are missing");
   while ((int)c->seg.size() < ck + 1) {
     FwdState f{};
     if (alloc_fwd(f, c) != hipSuccess) {
@@ -753,20 +793,10 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   te_status s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
-  const FwdState work = fwd_of(c->st);
-  // forward pass with checkpoints every ck iterations (state + the control record read by the next iteration)
-  c->state_scale = 0.0;  // the replay below overwrites the state a warm restart would continue from
-  HIPCHK(launch_init(c->prob, c->st, c->d_params, c->rec_warm ? c->d_x0rec : nullptr, 1.0 / c->scale,
-                     stream));
-  for (int k = 0; k < K; ++k) {
-    if (k % ck == 0) {
-      HIPCHK(copy_fwd(c->ckpt[k / ck], work, c, stream));
-      HIPCHK(hipMemcpyAsync(c->ckpt_ctrl[k / ck], c->st.ctrl + ((k + 1) & 1), sizeof(Ctrl),
-                            hipMemcpyDeviceToDevice, stream));
-    }
-    HIPCHK(launch_iteration(c->prob, c->st, c->d_params, k & 1, stream));
-  }
-  // reverse, segment by segment
+  const FwdState work = c->work;
+  c->state_scale = 0.0;  // the segment recomputation overwrites the state a warm restart would continue from
+  // reverse, segment by segment: restore the segment's checkpoint, recompute its iterations with
+  // the recorded schedule keeping every state, then run the adjoint iterations backwards
   HIPCHK(launch_adj_seed(c->prob, a, dS_dev, stream));
   for (int sgi = nck - 1; sgi >= 0; --sgi) {
     const int k0 = sgi * ck, k1 = std::min(K, k0 + ck);
@@ -792,16 +822,18 @@ void te_destroy(te_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
+  if (c->rec_chunk) (void)hipGraphExecDestroy(c->rec_chunk);
   for (auto &f : c->ckpt) free_fwd(f);
   for (auto &f : c->seg) free_fwd(f);
   for (Ctrl *p : c->ckpt_ctrl)
     if (p) (void)hipFree(p);
   {
-    void *ab[] = {c->adj.xb, c->adj.unb, c->adj.udb, c->adj.gb, c->adj.qb, c->adj.ab, c->d_log, c->d_x0rec};
+    void *ab[] = {c->adj.xb, c->adj.unb, c->adj.udb, c->adj.gb, c->adj.qb, c->adj.ab, c->d_log};
     for (void *p : ab)
       if (p) (void)hipFree(p);
   }
-  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.x, c->st.xf, c->st.uneg, c->st.udem, c->st.S, c->st.gq, c->st.ctrl,
+  free_fwd(c->work);
+  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.xf, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
                   c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab};
   for (void *b : bufs)
