@@ -113,6 +113,29 @@ def profile_run(args, torch, te, W, dev):
     log(f"iters {args.iters}: {st['ms']:.3f} ms")
 
 
+def probe_sync(torch, te, W, dev):
+    """Kernel boundaries against grid barriers on this GPU, with the per-iteration kernels' grid
+    shapes on the 150-node instance: microseconds per graph-replayed pair of near-empty kernels
+    (the graph engine's per-iteration structure) and per grid-wide barrier inside one co-resident
+    kernel (what a persistent kernel would pay twice per iteration)."""
+    import ctypes
+    inst = W.config2(0)
+    info = te.Problem(inst).info()
+    nA, nB = info["demand_workgroups"], info["link_workgroups"]
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_01748_amd", "libte_probe.so"))
+    lib.te_probe_sync.restype = ctypes.c_int
+    lib.te_probe_sync.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p]
+    out = np.zeros(3)
+    rc = lib.te_probe_sync(int(nA), 256, nB, 1024, 4096, out.ctypes.data)
+    if rc != 0:
+        raise SystemExit(f"te_probe_sync failed with HIP error {rc}")
+    res = {"workload": "near-empty kernels with the 150-node instance's launch shapes",
+           "demand_grid": f"{nA} x 256", "link_grid": f"{nB} x 1024",
+           "us_per_graph_kernel_pair": round(float(out[0]), 3), "us_per_grid_barrier": round(float(out[1]), 3),
+           "barrier_wait_bound_hit": bool(out[2])}
+    print(json.dumps(res), flush=True)
+
+
 def large_run(args, torch, te, W, dev):
     """The 1,000-node two-level WAN (50 regions x 20 nodes + backbone, all ~1M ordered pairs, k = 4):
     the size at which the per-iteration kernels move enough bytes for the HBM roofline to matter.
@@ -161,6 +184,7 @@ def main():
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--n-scen", type=int, default=512)
     ap.add_argument("--profile", choices=["copy", "iters"], default=None)
+    ap.add_argument("--probe-sync", action="store_true")
     ap.add_argument("--iters", type=int, default=64)
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--cache-dir", default=None)
@@ -184,6 +208,9 @@ def main():
         return
     if args.large:
         large_run(args, torch, te, W, dev)
+        return
+    if args.probe_sync:
+        probe_sync(torch, te, W, dev)
         return
 
     t0 = time.time()

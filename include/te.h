@@ -165,6 +165,16 @@ te_status te_solve(te_ctx *ctx, const te_options *opt, void *hip_stream, const f
                    float *S_out_dev, te_stats *stats);
 
 /*
+ * Feasible allocation from the state the handle's last graph-engine solve left: Algorithm 2
+ * (section 3.5) applied to its current rates at its final alpha, without iterating.  With
+ * te_solve(project = 0) and warm = 1 this gives an allocation at any point of a long solve.
+ *   x_out_dev [n_paths] float, S_out_dev nullable [n_demands] float: caller units.
+ * TE_ERR_STATE if there is no such state (none yet, te_grad / te_kernel_times ran since, or
+ * te_update changed the unit scale since: continue with warm = 1 first).
+ */
+te_status te_project(te_ctx *ctx, void *hip_stream, float *x_out_dev, float *S_out_dev);
+
+/*
  * Vector-Jacobian product through the last solve run with opt->record = 1 and
  * opt->fixed_iters = K: the unprojected sums S^(K) as a function of capacities
  * and demands, with the recorded (beta, alpha) schedule and the unit scale
@@ -204,8 +214,9 @@ te_status te_kernel_times(te_ctx *ctx, const te_options *opt, void *hip_stream, 
 void te_destroy(te_ctx *ctx);
 void te_destroy_batch(te_batch *batch);
 
-/* Sizes of a handle: n_links, n_paths, n_demands, nnz, max paths per demand, engine AUTO would pick. */
-te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [6] */);
+/* Sizes of a handle: n_links, n_paths, n_demands, nnz, max paths per demand, engine AUTO would pick,
+ * workgroups of the graph engine's demand kernel and of its link kernel. */
+te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [8] */);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *te_last_error(void);

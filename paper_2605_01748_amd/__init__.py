@@ -21,7 +21,8 @@ TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
 ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
-       "te_solve_batch", "te_kernel_times", "te_destroy", "te_destroy_batch", "te_info", "te_last_error"]
+       "te_solve_batch", "te_kernel_times", "te_project", "te_destroy", "te_destroy_batch", "te_info",
+       "te_last_error"]
 
 
 class TEError(RuntimeError):
@@ -81,6 +82,8 @@ def library(path: str = LIB_PATH):
     lib.te_create_batch.argtypes = [I, ctypes.POINTER(P), ctypes.POINTER(P)]
     lib.te_solve_batch.restype = I
     lib.te_solve_batch.argtypes = [P, ctypes.POINTER(_Options), P, P, P, P]
+    lib.te_project.restype = I
+    lib.te_project.argtypes = [P, P, P, P]
     lib.te_kernel_times.restype = I
     lib.te_kernel_times.argtypes = [P, ctypes.POINTER(_Options), P, I, P]
     lib.te_destroy.restype = None
@@ -191,10 +194,11 @@ class Problem:
         self.n_links, self.n_paths, self.n_demands = cap.shape[0], pptr.shape[0] - 1, dem.shape[0]
 
     def info(self):
-        sz = np.zeros(6, np.int64)
+        sz = np.zeros(8, np.int64)
         _check(library().te_info(self._h, sz.ctypes.data))
         return dict(n_links=int(sz[0]), n_paths=int(sz[1]), n_demands=int(sz[2]), nnz=int(sz[3]),
-                    max_paths=int(sz[4]), auto_engine=int(sz[5]))
+                    max_paths=int(sz[4]), auto_engine=int(sz[5]), demand_workgroups=int(sz[6]),
+                    link_workgroups=int(sz[7]))
 
     def update(self, capacity=None, demand=None):
         c = None if capacity is None else np.ascontiguousarray(capacity, np.float64)
@@ -234,6 +238,19 @@ class Problem:
         sp = _stream_ptr(dev) if stream is None else stream
         _check(library().te_grad(self._h, sp, dS.data_ptr(), dC.data_ptr(), dD.data_ptr()))
         return dC, dD
+
+    def project(self, x_out=None, S_out=None, stream=None):
+        """Feasible allocation (Algorithm 2) from the state the last graph-engine solve left (te_project):
+        returns (x [n_paths], S [n_demands]) float32 cuda tensors in caller units."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if x_out is None:
+            x_out = torch.empty(self.n_paths, dtype=torch.float32, device=dev)
+        if S_out is None:
+            S_out = torch.empty(self.n_demands, dtype=torch.float32, device=dev)
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_project(self._h, sp, x_out.data_ptr(), S_out.data_ptr()))
+        return x_out, S_out
 
     def kernel_times(self, opts: Options | None = None, iters: int = 64, stream=None):
         """Mean device time (ms) of the graph engine's demand and link kernels over `iters` iterations."""

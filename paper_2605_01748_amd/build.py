@@ -7,14 +7,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libte_gate.so")
 SOURCES = [os.path.join(HERE, "csrc", "te_kernels.hip"), os.path.join(HERE, "csrc", "te_runtime.cpp")]
+# measurement of kernel boundaries against grid barriers (bench.py --probe-sync)
+PROBE_LIB = os.path.join(HERE, "libte_probe.so")
+PROBE_SOURCES = [os.path.join(HERE, "csrc", "sync_probe.hip")]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(sources, out, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + FLAGS + ["-x", "hip"] + SOURCES + ["-o", LIB + ".tmp"]
+    cmd = [hipcc] + FLAGS + ["-x", "hip"] + sources + ["-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -23,7 +26,12 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed:\n{err}")
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

@@ -562,6 +562,8 @@ te_status te_info(const te_ctx *c, int64_t *sz) {
   sz[3] = c->nnz;
   sz[4] = c->maxp;
   sz[5] = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
+  sz[6] = c->st.nA;
+  sz[7] = c->st.nB;
   return TE_OK;
 }
 
@@ -747,6 +749,17 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
   if (err != hipSuccess) return fail(TE_ERR_DEVICE, "kernel timing: %s", hipGetErrorString(err));
   ms_out[0] = sd / iters;
   ms_out[1] = sl / iters;
+  return TE_OK;
+}
+
+te_status te_project(te_ctx *c, void *hip_stream, float *x_out_dev, float *S_out_dev) {
+  if (!c || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or output");
+  if (c->state_scale <= 0.0) return fail(TE_ERR_STATE, "no graph-engine state on this handle");
+  if (c->state_scale != c->scale)
+    return fail(TE_ERR_STATE, "te_update changed the unit scale since the last solve (continue with warm = 1 first)");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(launch_project(c->prob, c->st, c->pb, x_out_dev, S_out_dev, c->scale, 1, stream));
   return TE_OK;
 }
 

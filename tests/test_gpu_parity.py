@@ -427,3 +427,28 @@ def test_warm_needs_state(te, c1):
     with pytest.raises(te.TEError) as ex:
         prob.solve(te.Options(fixed_iters=10, warm=True))
     assert ex.value.status == te.TE_ERR_STATE
+
+
+def test_anytime_projection(te, c2):
+    """te_project on the state a solve left equals the projection te_solve applies at the end, and
+    interleaved with warm continuations gives a feasible allocation at every stop."""
+    prob = te.Problem(c2)
+    opts = dict(engine=te.ENGINE_GRAPH)
+    xp, Sp, _ = prob.solve(te.Options(fixed_iters=64, **opts))
+    prob.solve(te.Options(fixed_iters=64, project=False, **opts))
+    xa, Sa = prob.project()
+    np.testing.assert_array_equal(xa.cpu().numpy(), xp.cpu().numpy())
+    gold = np.load(_golden("maxmin_config2_s0.npz"))["S"]
+    scale = float(c2.capacity[np.unique(c2.path_links)].max())
+    last = None
+    for step in range(4):
+        prob.solve(te.Options(fixed_iters=128, project=False, warm=True, **opts))
+        x, S = prob.project()
+        x = x.cpu().numpy().astype(np.float64)
+        assert np.all(x >= 0)
+        assert np.all(O.link_loads(c2, x) <= c2.capacity * (1 + 1e-7))
+        assert np.all(O.demand_sums(c2, x) <= c2.demand * (1 + 1e-7))
+        opt = O.optimality(S.cpu().numpy().astype(np.float64), gold, 1e-9 * scale)
+        print(f"anytime: {64 + 128 * (step + 1)} iterations, optimality {opt:.4f}")
+        last = opt
+    assert last > 0.9
