@@ -34,7 +34,8 @@
  *    returns rates and sums in the caller's units.
  *  - Admissible instance (appendix C, Part I(b): every commodity has a path and
  *    a positive demand, every used link a positive capacity): at least one
- *    demand (an instance without commodities has nothing to solve), path_ptr
+ *    demand (an instance without commodities has nothing to solve), at most
+ *    524,288 links used by paths (the link kernel's work split), path_ptr
  *    non-decreasing from 0, no empty path, link ids in range, no link twice in
  *    one path, every demand with 1..64 paths, demand > 0 and finite, capacity
  *    finite everywhere and > 0 on every used link.  Anything else returns

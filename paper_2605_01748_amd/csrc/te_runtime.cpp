@@ -423,22 +423,33 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   }
   c->nzptr.push_back(c->nnz);
   {
+    // runs of whole links of about `target` entries (at most kMaxLinksPerBlock links); links larger
+    // than the target make runs of their own, so the target grows until at most kMaxLinkBlocks
+    // workgroups result (the control prefetch reads that many partial-sum rows)
     const int64_t want = std::min<int64_t>(kMaxLinkBlocks, std::max<int64_t>(1, (c->nnz + 4095) / 4096));
-    const int64_t target = std::max<int64_t>(1, (c->nnz + want - 1) / want);
-    int64_t cur = 0;
-    int cnt = 0;
-    c->blk.push_back(0);
-    for (size_t k = 0; k < c->nzlink.size(); ++k) {
-      const int64_t d = c->nzptr[k + 1] - c->nzptr[k];
-      if (cnt > 0 && (cur + d > target || cnt == kMaxLinksPerBlock)) {
-        c->blk.push_back((int32_t)k);
-        cur = 0;
-        cnt = 0;
+    int64_t target = std::max<int64_t>(1, (c->nnz + want - 1) / want);
+    for (;;) {
+      c->blk.assign(1, 0);
+      int64_t cur = 0;
+      int cnt = 0;
+      for (size_t k = 0; k < c->nzlink.size(); ++k) {
+        const int64_t d = c->nzptr[k + 1] - c->nzptr[k];
+        if (cnt > 0 && (cur + d > target || cnt == kMaxLinksPerBlock)) {
+          c->blk.push_back((int32_t)k);
+          cur = 0;
+          cnt = 0;
+        }
+        cur += d;
+        ++cnt;
       }
-      cur += d;
-      ++cnt;
+      c->blk.push_back((int32_t)c->nzlink.size());
+      if ((int64_t)c->blk.size() - 1 <= kMaxLinkBlocks) break;
+      if (target >= (int64_t)c->nnz) {  // only reachable with more than kMaxLinkBlocks * kMaxLinksPerBlock links
+        te_destroy(c);
+        return fail(TE_ERR_INVALID, "more than %d used links", kMaxLinkBlocks * kMaxLinksPerBlock);
+      }
+      target += target / 8 + 1;
     }
-    c->blk.push_back((int32_t)c->nzlink.size());
   }
   const int nB = (int)c->blk.size() - 1;
   // per-wavefront parts of each workgroup's CSC entries (the split the link kernels use)

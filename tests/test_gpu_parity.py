@@ -111,6 +111,8 @@ def test_parity_hierarchical_full_size(te):
     K = 16
     r, sb, sa = _oracle_run(inst, K)
     prob = te.Problem(inst)
+    # the link kernel's workgroups stay within the rows the control prefetch reads
+    assert prob.info()["link_workgroups"] <= 512
     x, S, st = _gpu_raw(te, prob, K, sb, sa, te.ENGINE_GRAPH)
     assert st["iters"] == K
     err = _report(f"hierarchical 1000-node graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, inst.demand)
