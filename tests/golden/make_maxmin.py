@@ -3,7 +3,7 @@
 Inputs come from the seeded generators (``workloads``); the allocations come only from
 ``oracle.maxmin_exact`` (progressive filling of LPs, HiGHS).  Run from the repository root:
 
-    python tests/golden/make_maxmin.py config1 config2
+    python tests/golden/make_maxmin.py config1 config2 config4
 """
 import os
 import sys
@@ -18,8 +18,25 @@ import workloads  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def scenarios(n=512):
+    """Exact max-min allocations of the n failure scenarios (seed 0) of the 20-node instance."""
+    scen = workloads.config4_scenarios(0, n_scen=n)
+    out = {}
+    for i, inst in enumerate(scen):
+        S, info = oracle.maxmin_exact(inst)
+        out[f"S{i}"] = S
+        out[f"fp{i}"] = np.array(inst.fingerprint())
+        print(f"scenario {i}: {inst.summary()} {info}", flush=True)
+    path = os.path.join(HERE, "maxmin_config4_s0.npz")
+    np.savez_compressed(path, n=np.array(n), **out)
+    print(f"wrote {path}", flush=True)
+
+
 def main(names):
     for name in names:
+        if name == "config4":
+            scenarios()
+            continue
         inst = getattr(workloads, name)(0)
         print(inst.summary(), flush=True)
         S, info = oracle.maxmin_exact(inst, verbose=True)

@@ -454,3 +454,38 @@ def test_anytime_projection(te, c2):
         print(f"anytime: {64 + 128 * (step + 1)} iterations, optimality {opt:.4f}")
         last = opt
     assert last > 0.9
+
+
+@pytest.mark.parametrize("engine", ["block", "graph"])
+@pytest.mark.parametrize("K", [1, 2, 16, 256])
+def test_parity_fixed_beta_fixed_alpha(te, c1, engine, K):
+    """beta held at beta0 and alpha held at 0 (no adaptation at all): the plain iteration."""
+    o = dict(fixed_iters=K, project=False, adapt_beta=False, alpha_target=0.0)
+    r = O.solve(c1, O.Options(**o), want_state=False)
+    sb, sa = r.schedule
+    assert np.all(sb == 1.0) and np.all(sa == 0.0)
+    prob = te.Problem(c1)
+    eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
+    x, S, st = prob.solve(te.Options(engine=eng, **o))
+    err = _report(f"config1 fixed beta/alpha {engine} K={K}", S.cpu().numpy().astype(np.float64),
+                  r.S_raw * r.scale, c1.demand)
+    assert err.max() <= REL
+
+
+def test_failure_scenarios_reach_maxmin(te):
+    """The batched solve of the first 64 failure scenarios: every scenario within 1 % of its exact
+    max-min allocation (progressive-filling LPs, tests/golden) after 1,000 iterations."""
+    g = np.load(_golden("maxmin_config4_s0.npz"))
+    scen = W.config4_scenarios(0, n_scen=64)
+    batch = te.Batch([te.Problem(s) for s in scen])
+    _, S, _ = batch.solve(te.Options(fixed_iters=1000))
+    S = S.cpu().numpy().astype(np.float64)
+    off = 0
+    worst = 1.0
+    for i, inst in enumerate(scen):
+        assert str(g[f"fp{i}"]) == inst.fingerprint()
+        opt = O.optimality(S[off:off + inst.n_demands], g[f"S{i}"], 1e-9 * 100.0)
+        worst = min(worst, opt)
+        off += inst.n_demands
+    print(f"64 failure scenarios, 1000 iterations: worst optimality {worst:.5f}")
+    assert worst >= 0.99

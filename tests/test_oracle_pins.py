@@ -128,6 +128,40 @@ def test_sum_root_alpha2_cubic():
     assert checked > 10
 
 
+@pytest.mark.parametrize("alpha", [0.0, 1.0, 3.0])
+def test_sum_root_any_warm_start_and_brute_force(alpha):
+    """The safeguarded Newton root does not depend on its warm start (bracket growth from far below
+    and far above, halving towards 0 for alpha > 0), and equals a plain 300-step bisection of the
+    sum equation (F decreasing; appendix B.2) on the same data."""
+    rng = np.random.default_rng(11 + int(alpha))
+    for _ in range(25):
+        m = int(rng.integers(1, 9))
+        n = rng.integers(1, 9, m)
+        uneg = rng.uniform(0.0, 0.5, m) * (rng.uniform(size=m) < 0.5)
+        a = rng.uniform(-1.0, 2.0, m)
+        D = float(rng.uniform(0.01, 2.0))
+        udem = float(rng.uniform(0.0, 0.5)) * float(rng.uniform() < 0.5)
+        beta = float(10.0 ** rng.uniform(-2, 2))
+
+        def F(S):
+            h = max(S - D + udem, 0.0) - (S ** -alpha if alpha > 0 else 1.0) / beta
+            b = a - h
+            x = np.where(b >= n * uneg, b / n, (b + uneg) / (n + 1))
+            return x.sum() - S
+
+        lo, hi = (1e-60, 1e6) if alpha > 0 else (-1e6, 1e6)
+        assert F(lo) > 0 > F(hi)
+        for _ in range(300):
+            mid = 0.5 * (lo + hi)
+            if F(mid) > 0:
+                lo = mid
+            else:
+                hi = mid
+        roots = [O.sum_root(a, n, uneg, D, udem, alpha, beta, S0)[0] for S0 in (1e-9, 1e-3, 1.0, 1e3, 1e6)]
+        for r in roots:
+            assert r == pytest.approx(lo, rel=1e-10, abs=1e-13)
+
+
 # ------------------------------------------------------------------------------------------
 # y-block: one link, read back from the oracle after one and two sweeps
 # ------------------------------------------------------------------------------------------
