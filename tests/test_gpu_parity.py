@@ -85,7 +85,7 @@ def test_parity_config1(te, c1, engine, K):
     assert err.max() <= REL
 
 
-@pytest.mark.parametrize("K", [16, 256, 861])  # 861: the budget the benchmark times (first to reach 0.99)
+@pytest.mark.parametrize("K", [16, 256, 833])  # 833: the budget the benchmark times (first to reach 0.99)
 def test_parity_config2_graph(te, c2, K):
     r, sb, sa = _oracle_run(c2, K)
     prob = te.Problem(c2)
