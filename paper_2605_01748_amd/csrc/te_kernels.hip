@@ -70,6 +70,17 @@ __device__ __forceinline__ void finish_ctrl(CtrlPrefetch &cp, const Params &prm,
   if (threadIdx.x == 0) *out = decide(cp.prev, cp.v, prm);
 }
 
+// XCD-aware work order.  The dispatcher deals the workgroups of a launch round-robin over the 8
+// XCDs (workgroup b runs on XCD b % 8, each XCD with its own L2).  Processing logical block
+// xcd_chunk(b) instead of b gives every XCD one contiguous range of the logical work: the demand
+// kernel's blocks of consecutive demands and the link kernel's blocks of consecutive links then
+// touch compact parts of the path arrays per XCD (one less trip to the memory side for what the
+// same XCD wrote or read before).  A bijection of [0, n).
+__device__ __forceinline__ int xcd_chunk(int b, int n) {
+  const int x = b & 7, i = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + i;
+}
+
 // block-wide reduction of 4 partials (sum, sum, max, max) into dst[0..3] by thread 0
 __device__ void block_partials(double p0, double p1, double p2, double p3, double *dst) {
   __shared__ double red[4][16];
@@ -176,7 +187,8 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
   const int G = p.G;
   const int t = threadIdx.x;
   const int lane = t & (G - 1);
-  const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int c = bl * (kThreads >> p.logG) + (t >> p.logG);
   // gathers (independent of the control record): sums of g and q along the path
   int r0 = 0, np = 0, r = 0, n = 1;
   double xr = 0.0, ung = 0.0, Dc = 0.0;
@@ -248,7 +260,7 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
       dem_v = (Ssum - dm.D) / dm.D;
     }
   }
-  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + blockIdx.x) * 4);
+  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + bl) * 4);
 }
 
 // CSC entry encodings: int32 (graph engine) with bit 31 on a link's first entry, uint16 (workgroup
@@ -314,8 +326,9 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   CtrlPrefetch cp;
   if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int4 wt = p.wtab[blockIdx.x * kLinkWaves + w];
-  const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int4 wt = p.wtab[bl * kLinkWaves + w];
+  const int k0 = p.blk[bl], k1 = p.blk[bl + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   // the per-link values of this thread's first link and its slice of the demand kernel's
   // partial sums are loaded before the segmented sums, so their latency overlaps with them
@@ -332,7 +345,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
   if (w == 1) {  // fold the demand kernel's rows b, b + nB, ... (fixed order)
     const double *pa = s.partA + (size_t)par * s.nA * 4;
-    for (int i = blockIdx.x + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
+    for (int i = bl + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
       a0 += pa[4 * i + 0];
       a1 += pa[4 * i + 1];
       a3 = fmax(a3, pa[4 * i + 3]);
@@ -371,7 +384,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
     cap_v = fmax(cap_v, (load - Ce) / Ce);
   }
-  block_partials(a0, dr2 + a1, cap_v, a3, s.partB + ((size_t)par * s.nB + blockIdx.x) * 4);
+  block_partials(a0, dr2 + a1, cap_v, a3, s.partB + ((size_t)par * s.nB + bl) * 4);
 }
 
 // Final control record: applies the decision pending after the last iteration.
@@ -927,7 +940,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, F
   const int G = p.G;
   const int t = threadIdx.x;
   const int lane = t & (G - 1);
-  const int c = blockIdx.x * (kThreads >> p.logG) + (t >> p.logG);
+  const int c = xcd_chunk(blockIdx.x, gridDim.x) * (kThreads >> p.logG) + (t >> p.logG);
   if (c >= p.D) return;  // uniform in the lane group
   const int r0 = p.dptr[c], np = p.dptr[c + 1] - r0;
   const bool on = lane < np;
@@ -1002,8 +1015,9 @@ __global__ __launch_bounds__(kThreads) void k_adj_demand(Prob p, FwdState fin, F
 
 __global__ __launch_bounds__(kLinkThreads) void k_adj_link(Prob p, FwdState fout, AdjState a, double rho) {
   __shared__ double acc[kMaxLinksPerBlock];
-  const int4 wt = p.wtab[blockIdx.x * kLinkWaves + (threadIdx.x >> 6)];
-  const int k0 = p.blk[blockIdx.x], k1 = p.blk[blockIdx.x + 1];
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int4 wt = p.wtab[bl * kLinkWaves + (threadIdx.x >> 6)];
+  const int k0 = p.blk[bl], k1 = p.blk[bl + 1];
   for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc[k] = 0.0;
   __syncthreads();
   seg_rows_sum(p.lpf, a.ab, k0, wt, acc);
