@@ -43,6 +43,17 @@ def log(*a):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_demand_k_link_150node_traffic.md")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def optimality(S, opt, theta):
     """The paper's optimality metric (section 4.1): mean over demands of min(S_d / max(OPT_d, theta), 1)."""
     S = np.asarray(S, np.float64)
@@ -307,7 +318,7 @@ def main():
         floor = 1e-2 * inst.demand.max()
         err = np.abs(S_rep - orc_S) / np.maximum(np.abs(orc_S), floor)
         cpu = {"value": round(t_orc * 1e3, 1), "unit": "ms", "cores": int(os.environ.get("OMP_NUM_THREADS", threads)),
-               "kind": "oracle",
+               "kind": "oracle", "cpu": cpu_model(),
                "sample": f"{n_orc} full FP64 oracle solves of the same instance at K*={K_star} iterations "
                          f"(OpenMP, {os.environ.get('OMP_NUM_THREADS')} threads); mean ms per solve",
                "oracle_optimality": round(optimality(r.S, opt_S, THETA * scale), 5),
@@ -421,6 +432,7 @@ def main():
                                "1.3x max concurrent flow, k=8 latency-shortest paths, max-min target",
                    "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
                    "K_star": K_star, "optimality": round(opt_at, 5), "engine": "graph",
+                   "solves_per_s": round(1e3 / ms_per_step, 2),
                    "median_event_ms": round(float(np.median(ev_ms)), 4)},
         "roofline": roofline,
         "cpu_baseline": cpu,

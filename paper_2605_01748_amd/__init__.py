@@ -317,7 +317,13 @@ class Batch:
             pass
 
 
+_GATE_SOLVE = None
+
+
 def _autograd_function():
+    global _GATE_SOLVE
+    if _GATE_SOLVE is not None:
+        return _GATE_SOLVE
     import torch
 
     class GateSolve(torch.autograd.Function):
@@ -341,6 +347,7 @@ def _autograd_function():
             dC, dD = ctx.problem.grad(gS)
             return None, dC.cpu(), dD.cpu(), None, None
 
+    _GATE_SOLVE = GateSolve
     return GateSolve
 
 

@@ -489,3 +489,23 @@ def test_failure_scenarios_reach_maxmin(te):
         off += inst.n_demands
     print(f"64 failure scenarios, 1000 iterations: worst optimality {worst:.5f}")
     assert worst >= 0.99
+
+
+def test_gatesolve_matches_oracle_reverse_pass(te, c1, torch):
+    """torch.autograd through GateSolve (te_update + recorded te_solve + te_grad) gives the FP64
+    reverse pass of the oracle for a weighted sum of the sums, with the oracle's schedule replayed."""
+    import torch as t
+    K = 64
+    r, sb, sa = _oracle_run(c1, K)
+    prob = te.Problem(c1)
+    C = t.tensor(c1.capacity, dtype=t.float64, requires_grad=True)
+    D = t.tensor(c1.demand, dtype=t.float64, requires_grad=True)
+    w = np.random.default_rng(4).uniform(0.5, 1.5, c1.n_demands)
+    S = te.GateSolve.apply(prob, C, D, K, te.Options(engine=te.ENGINE_GRAPH, sched_beta=sb, sched_alpha=sa))
+    (S.double().cpu() * t.tensor(w)).sum().backward()
+    _, oC, oD = O.grad(c1, sb, sa, w.astype(np.float32).astype(np.float64))
+    scale = max(np.abs(oC).max(), np.abs(oD).max())
+    eC = np.abs(C.grad.numpy() - oC).max() / scale
+    eD = np.abs(D.grad.numpy() - oD).max() / scale
+    print(f"GateSolve K={K}: max |err| / max |grad|: dC {eC:.2e} dD {eD:.2e}")
+    assert eC <= 1e-3 and eD <= 1e-3
