@@ -114,7 +114,7 @@ def profile_run(args, torch, te, W, dev):
         torch.cuda.synchronize()
         log(f"copy: 5 x {4 * n} bytes")
         return
-    inst = W.config2(0)
+    inst = W.waxman150(0)
     log(inst.summary())
     prob = te.Problem(inst)
     o = te.Options(fixed_iters=args.iters, project=False, engine=te.ENGINE_GRAPH)
@@ -130,7 +130,7 @@ def probe_sync(torch, te, W, dev):
     (the graph engine's per-iteration structure) and per grid-wide barrier inside one co-resident
     kernel (what a persistent kernel would pay twice per iteration)."""
     import ctypes
-    inst = W.config2(0)
+    inst = W.waxman150(0)
     info = te.Problem(inst).info()
     nA, nB = info["demand_workgroups"], info["link_workgroups"]
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2605_01748_amd", "libte_probe.so"))
@@ -160,7 +160,7 @@ def large_run(args, torch, te, W, dev):
             last[0] = time.time()
             log(f"  k-shortest paths: {done}/{total} pairs ({time.time() - t0:.0f}s)")
 
-    inst = W.config3(0, cache_dir=args.cache_dir, progress=progress)
+    inst = W.two_level1000(0, cache_dir=args.cache_dir, progress=progress)
     log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
     prob = te.Problem(inst)
     ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=32)
@@ -225,8 +225,8 @@ def main():
         return
 
     t0 = time.time()
-    inst = W.config2(0)
-    gold = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_config2_s0.npz"))
+    inst = W.waxman150(0)
+    gold = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_waxman150_s0.npz"))
     assert str(gold["fingerprint"]) == inst.fingerprint(), "instance does not match the stored max-min allocation"
     opt_S = gold["S"]
     log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
@@ -329,8 +329,8 @@ def main():
     batch = None
     if not args.no_batch:
         t2 = time.time()
-        scen = W.config4_scenarios(0, n_scen=args.n_scen)
-        gold4 = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_config4_s0.npz"))
+        scen = W.failure_scenarios(0, n_scen=args.n_scen)
+        gold4 = np.load(os.path.join(ROOT, "tests", "golden", "maxmin_failures_s0.npz"))
         n_gold = min(len(scen), int(gold4["n"]))
         for i in range(n_gold):
             assert str(gold4[f"fp{i}"]) == scen[i].fingerprint(), "scenario does not match its stored max-min"
@@ -379,13 +379,13 @@ def main():
                  "batched_scenarios_per_s": round(len(probs) / t_batch, 1),
                  "plain_scenarios_per_s": round(1.0 / t_plain, 1),
                  "speedup": round((len(probs) / t_batch) * t_plain, 2), "batch_workgroup_threads": wg,
-                 "workload": "config-1 topology, 1-3 link cuts, lognormal(0,0.3) demand noise, k_c in 2..8"}
+                 "workload": "20-node Waxman topology, 1-3 link cuts, lognormal(0,0.3) demand noise, k_c in 2..8"}
         log(f"batch: {batch} ({time.time() - t2:.1f}s)")
 
     # ---- differentiation: te_grad through a recorded 256-iteration solve of the 20-node instance ----
     grad = None
     if not args.no_grad:
-        c1 = W.config1(0)
+        c1 = W.waxman20(0)
         p1 = te.Problem(c1)
         Kg = 256
         og = te.Options(fixed_iters=Kg, project=False, record=True, ckpt_every=16)
@@ -428,7 +428,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "config2: 150-node Waxman, ~600 links, 22350 gravity demands (lognormal 1.5), "
+        "config": {"workload": "waxman150: 150-node Waxman, ~600 links, 22350 gravity demands (lognormal 1.5), "
                                "1.3x max concurrent flow, k=8 latency-shortest paths, max-min target",
                    "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
                    "K_star": K_star, "optimality": round(opt_at, 5), "engine": "graph",

@@ -18,6 +18,6 @@ def pytest_configure(config):
 
 
 @pytest.fixture(scope="session")
-def config1():
+def waxman20():
     import workloads
-    return workloads.config1(0)
+    return workloads.waxman20(0)

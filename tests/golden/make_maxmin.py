@@ -3,7 +3,7 @@
 Inputs come from the seeded generators (``workloads``); the allocations come only from
 ``oracle.maxmin_exact`` (progressive filling of LPs, HiGHS).  Run from the repository root:
 
-    python tests/golden/make_maxmin.py config1 config2 config4
+    python tests/golden/make_maxmin.py waxman20 waxman150 failures
 """
 import os
 import sys
@@ -20,21 +20,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def scenarios(n=512):
     """Exact max-min allocations of the n failure scenarios (seed 0) of the 20-node instance."""
-    scen = workloads.config4_scenarios(0, n_scen=n)
+    scen = workloads.failure_scenarios(0, n_scen=n)
     out = {}
     for i, inst in enumerate(scen):
         S, info = oracle.maxmin_exact(inst)
         out[f"S{i}"] = S
         out[f"fp{i}"] = np.array(inst.fingerprint())
         print(f"scenario {i}: {inst.summary()} {info}", flush=True)
-    path = os.path.join(HERE, "maxmin_config4_s0.npz")
+    path = os.path.join(HERE, "maxmin_failures_s0.npz")
     np.savez_compressed(path, n=np.array(n), **out)
     print(f"wrote {path}", flush=True)
 
 
 def main(names):
     for name in names:
-        if name == "config4":
+        if name == "failures":
             scenarios()
             continue
         inst = getattr(workloads, name)(0)
@@ -47,4 +47,4 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["config1", "config2"])
+    main(sys.argv[1:] or ["waxman20", "waxman150"])

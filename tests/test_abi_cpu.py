@@ -37,7 +37,7 @@ def _inst():
 
 def test_valid_instance_passes():
     te.validate(_inst())
-    te.validate(W.config1(0))
+    te.validate(W.waxman20(0))
 
 
 @pytest.mark.parametrize("mutate,needle", [

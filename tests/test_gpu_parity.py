@@ -38,12 +38,12 @@ def te(torch):
 
 @pytest.fixture(scope="module")
 def c1():
-    return W.config1(0)
+    return W.waxman20(0)
 
 
 @pytest.fixture(scope="module")
 def c2():
-    return W.config2(0)
+    return W.waxman150(0)
 
 
 def _oracle_run(inst, K, **kw):
@@ -75,23 +75,23 @@ def _gpu_raw(te, prob, K, sb, sa, engine):
 
 @pytest.mark.parametrize("engine", ["block", "graph"])
 @pytest.mark.parametrize("K", [1, 2, 16, 256])
-def test_parity_config1(te, c1, engine, K):
+def test_parity_waxman20(te, c1, engine, K):
     r, sb, sa = _oracle_run(c1, K)
     prob = te.Problem(c1)
     eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
     x, S, st = _gpu_raw(te, prob, K, sb, sa, eng)
     assert st["iters"] == K and st["engine"] == eng
-    err = _report(f"config1 {engine} K={K}", S, r.S_raw * r.scale, c1.demand)
+    err = _report(f"waxman20 {engine} K={K}", S, r.S_raw * r.scale, c1.demand)
     assert err.max() <= REL
 
 
 @pytest.mark.parametrize("K", [16, 256, 833])  # 833: the budget the benchmark times (first to reach 0.99)
-def test_parity_config2_graph(te, c2, K):
+def test_parity_waxman150_graph(te, c2, K):
     r, sb, sa = _oracle_run(c2, K)
     prob = te.Problem(c2)
     x, S, st = _gpu_raw(te, prob, K, sb, sa, te.ENGINE_GRAPH)
     assert st["iters"] == K
-    err = _report(f"config2 graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, c2.demand)
+    err = _report(f"waxman150 graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, c2.demand)
     assert err.max() <= REL
 
 
@@ -99,14 +99,14 @@ def test_parity_config2_graph(te, c2, K):
 def c3_small():
     # the two-level WAN generator at 6 regions (120 nodes, ~1,150 arcs, 14,280 pairs, k = 4):
     # same structure as the 1,000-node instance, at a size the oracle runs in a fraction of a second
-    return W.config3(1, regions=6, backbone_links=120)
+    return W.two_level1000(1, regions=6, backbone_links=120)
 
 
 @pytest.mark.slow
 def test_parity_hierarchical_full_size(te):
     """The 1,000-node two-level instance (999,000 demands, ~4.0M paths, ~23.5M incidences) after 16
     iterations, every demand against the oracle."""
-    inst = W.config3(0)
+    inst = W.two_level1000(0)
     print(inst.summary(), flush=True)
     K = 16
     r, sb, sa = _oracle_run(inst, K)
@@ -170,7 +170,7 @@ def test_parity_finite_alpha_targets(te, c1, engine, alpha):
     prob = te.Problem(c1)
     eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
     x, S, st = _gpu_raw(te, prob, K, sb, sa, eng)
-    err = _report(f"config1 alpha={alpha} {engine}", S, r.S_raw * r.scale, c1.demand)
+    err = _report(f"waxman20 alpha={alpha} {engine}", S, r.S_raw * r.scale, c1.demand)
     assert err.max() <= REL
 
 
@@ -192,7 +192,7 @@ def test_adaptive_stop_proportional(te, c1, engine):
 
 
 @pytest.mark.parametrize("engine", ["block", "graph"])
-def test_projection_config1(te, c1, engine):
+def test_projection_waxman20(te, c1, engine):
     K = 300
     eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
     prob = te.Problem(c1)
@@ -212,7 +212,7 @@ def test_projection_config1(te, c1, engine):
     np.testing.assert_allclose(xp, ref, rtol=2e-6, atol=1e-6 * c1.capacity.max())
 
 
-def test_projection_config2_graph(te, c2):
+def test_projection_waxman150_graph(te, c2):
     K = 64
     prob = te.Problem(c2)
     r, sb, sa = _oracle_run(c2, K)
@@ -230,13 +230,13 @@ def test_projection_config2_graph(te, c2):
                                atol=1e-6 * c2.capacity.max())
 
 
-def test_adaptive_solve_reaches_maxmin_config1(te, c1):
-    gold = np.load(_golden("maxmin_config1_s0.npz"))["S"]
+def test_adaptive_solve_reaches_maxmin_waxman20(te, c1):
+    gold = np.load(_golden("maxmin_waxman20_s0.npz"))["S"]
     prob = te.Problem(c1)
     x, S, st = prob.solve(te.Options(fixed_iters=600))
     S = S.cpu().numpy().astype(np.float64)
     opt = O.optimality(S, gold, 1e-9)
-    print(f"config1 K=600 optimality {opt:.5f} alpha {st['final_alpha']} beta {st['beta']}")
+    print(f"waxman20 K=600 optimality {opt:.5f} alpha {st['final_alpha']} beta {st['beta']}")
     assert opt >= 0.99
 
 
@@ -244,7 +244,7 @@ def test_adaptive_solve_reaches_maxmin_config1(te, c1):
 def test_batch_equals_individual(te, threads):
     """One launch over uneven instances gives each the same rates as its own workgroup-engine solve
     with the same workgroup size (bit for bit)."""
-    scen = W.config4_scenarios(0, n_scen=24)
+    scen = W.failure_scenarios(0, n_scen=24)
     probs = [te.Problem(s) for s in scen]
     batch = te.Batch(probs)
     opts = te.Options(fixed_iters=200, block_threads=threads)
@@ -269,7 +269,7 @@ def test_parity_block_workgroup_sizes(te, c1, threads):
                       sched_beta=sb, sched_alpha=sa)
     x, S, st = prob.solve(opts)
     assert st["block_threads"] == threads
-    err = _report(f"config1 block threads={threads}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
+    err = _report(f"waxman20 block threads={threads}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
                   c1.demand)
     assert err.max() <= REL
 
@@ -277,7 +277,7 @@ def test_parity_block_workgroup_sizes(te, c1, threads):
 def test_batch_tuned_workgroup_size(te):
     """block_threads = 0 on a batch: the size measured fastest on the first solve is kept, and the
     result equals the forced solve at that size."""
-    scen = W.config4_scenarios(1, n_scen=64)
+    scen = W.failure_scenarios(1, n_scen=64)
     batch = te.Batch([te.Problem(s) for s in scen])
     x1, _, st1 = batch.solve(te.Options(fixed_iters=64))
     t = st1[0]["block_threads"]
@@ -318,7 +318,7 @@ def _golden(name):
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
 
 
-@pytest.mark.parametrize("which,K", [("tiny", 40), ("config1", 256)])
+@pytest.mark.parametrize("which,K", [("tiny", 40), ("waxman20", 256)])
 def test_grad_matches_oracle_reverse_pass(te, c1, which, K):
     """te_grad (adjoint kernels, checkpoints every 16 iterations) against the oracle's FP64 reverse
     pass with the same replayed schedule: total throughput (cotangent 1) and sum of logs (1/S)."""
@@ -440,7 +440,7 @@ def test_anytime_projection(te, c2):
     prob.solve(te.Options(fixed_iters=64, project=False, **opts))
     xa, Sa = prob.project()
     np.testing.assert_array_equal(xa.cpu().numpy(), xp.cpu().numpy())
-    gold = np.load(_golden("maxmin_config2_s0.npz"))["S"]
+    gold = np.load(_golden("maxmin_waxman150_s0.npz"))["S"]
     scale = float(c2.capacity[np.unique(c2.path_links)].max())
     last = None
     for step in range(4):
@@ -467,7 +467,7 @@ def test_parity_fixed_beta_fixed_alpha(te, c1, engine, K):
     prob = te.Problem(c1)
     eng = te.ENGINE_BLOCK if engine == "block" else te.ENGINE_GRAPH
     x, S, st = prob.solve(te.Options(engine=eng, **o))
-    err = _report(f"config1 fixed beta/alpha {engine} K={K}", S.cpu().numpy().astype(np.float64),
+    err = _report(f"waxman20 fixed beta/alpha {engine} K={K}", S.cpu().numpy().astype(np.float64),
                   r.S_raw * r.scale, c1.demand)
     assert err.max() <= REL
 
@@ -475,8 +475,8 @@ def test_parity_fixed_beta_fixed_alpha(te, c1, engine, K):
 def test_failure_scenarios_reach_maxmin(te):
     """The batched solve of the first 64 failure scenarios: every scenario within 1 % of its exact
     max-min allocation (progressive-filling LPs, tests/golden) after 1,000 iterations."""
-    g = np.load(_golden("maxmin_config4_s0.npz"))
-    scen = W.config4_scenarios(0, n_scen=64)
+    g = np.load(_golden("maxmin_failures_s0.npz"))
+    scen = W.failure_scenarios(0, n_scen=64)
     batch = te.Batch([te.Problem(s) for s in scen])
     _, S, _ = batch.solve(te.Options(fixed_iters=1000))
     S = S.cpu().numpy().astype(np.float64)

@@ -42,12 +42,12 @@ def _max_single(inst, c, lower):
     return -res.fun
 
 
-@pytest.mark.parametrize("which", ["config1", "tiny0", "tiny1"])
+@pytest.mark.parametrize("which", ["waxman20", "tiny0", "tiny1"])
 def test_definition_no_commodity_can_rise(which):
     """The max-min definition itself: raising any S_c forces lowering some S_c' <= S_c.
     For each c: max S_c subject to every c' with OPT_c' <= OPT_c keeping OPT_c' equals OPT_c."""
-    if which == "config1":
-        inst = W.config1(0)
+    if which == "waxman20":
+        inst = W.waxman20(0)
     else:
         import sys
         import os

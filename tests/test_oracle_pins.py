@@ -178,8 +178,8 @@ def _link_min(C, ucap, ucon, x):
     return res.x[:m]
 
 
-def test_y_block_is_exact_minimiser(config1):
-    inst = config1
+def test_y_block_is_exact_minimiser(waxman20):
+    inst = waxman20
     opt = O.Options(fixed_iters=1, project=False, adapt_beta=False)
     r1 = O.solve(inst, opt)
     r2 = O.solve(inst, O.Options(fixed_iters=2, project=False, adapt_beta=False))
@@ -325,78 +325,78 @@ def test_projection_parallel_links_take_max():
     np.testing.assert_allclose(xp, [0.4, 0.6, 0.45], atol=1e-15)
 
 
-def test_projection_invariants_random(config1):
+def test_projection_invariants_random(waxman20):
     rng = np.random.default_rng(3)
-    x = rng.uniform(-0.5, 3.0, config1.n_paths) * rng.uniform(size=config1.n_paths) ** 2 * 10
-    xp = O.project(config1, x, 2.0)
+    x = rng.uniform(-0.5, 3.0, waxman20.n_paths) * rng.uniform(size=waxman20.n_paths) ** 2 * 10
+    xp = O.project(waxman20, x, 2.0)
     assert np.all(xp >= 0)
-    S = O.demand_sums(config1, xp)
-    L = O.link_loads(config1, xp)
-    assert np.all(S <= config1.demand * (1 + 1e-12))
-    assert np.all(L <= config1.capacity * (1 + 1e-9))
+    S = O.demand_sums(waxman20, xp)
+    L = O.link_loads(waxman20, xp)
+    assert np.all(S <= waxman20.demand * (1 + 1e-12))
+    assert np.all(L <= waxman20.capacity * (1 + 1e-9))
     assert np.all(xp <= np.maximum(x, 0) + 1e-15)
 
 
 # ------------------------------------------------------------------------------------------
 # whole-solve invariants and identities
 # ------------------------------------------------------------------------------------------
-def test_consensus_duals_collapse(config1):
-    r = O.solve(config1, O.Options(fixed_iters=300, project=False))
+def test_consensus_duals_collapse(waxman20):
+    r = O.solve(waxman20, O.Options(fixed_iters=300, project=False))
     assert r.collapse_dev < 1e-12
     # after each sweep y_{e,r} = x_r + q_e with one offset q_e per link
-    path_of_inc = np.repeat(np.arange(config1.n_paths), np.diff(config1.path_ptr))
+    path_of_inc = np.repeat(np.arange(waxman20.n_paths), np.diff(waxman20.path_ptr))
     q = r.y - r.x_raw[path_of_inc]
-    for e in range(config1.n_links):
-        qe = q[config1.path_links == e]
+    for e in range(waxman20.n_links):
+        qe = q[waxman20.path_links == e]
         if len(qe):
             assert np.ptp(qe) < 1e-12
 
 
-def test_collapsed_matches_full(config1):
-    full = O.solve(config1, O.Options(fixed_iters=300, project=False))
+def test_collapsed_matches_full(waxman20):
+    full = O.solve(waxman20, O.Options(fixed_iters=300, project=False))
     sb, sa = full.schedule
     opts = dict(fixed_iters=300, project=False, sched_beta=sb, sched_alpha=sa)
-    a = O.solve(config1, O.Options(**opts))
-    b = O.solve(config1, O.Options(collapsed=True, **opts))
+    a = O.solve(waxman20, O.Options(**opts))
+    b = O.solve(waxman20, O.Options(collapsed=True, **opts))
     np.testing.assert_allclose(a.x_raw, full.x_raw, rtol=0, atol=1e-13)
     # same algebra, different summation order: agreement to rounding accumulated over 300 sweeps
     np.testing.assert_allclose(b.x_raw, a.x_raw, rtol=0, atol=1e-9)
     np.testing.assert_allclose(b.S_raw, a.S_raw, rtol=0, atol=1e-9)
 
 
-def test_projected_solution_feasible_and_near_maxmin(config1):
-    gold = np.load(_golden("maxmin_config1_s0.npz"))
-    assert str(gold["fingerprint"]) == config1.fingerprint()
-    r = O.solve(config1, O.Options(fixed_iters=1500))
-    L = O.link_loads(config1, r.x)
+def test_projected_solution_feasible_and_near_maxmin(waxman20):
+    gold = np.load(_golden("maxmin_waxman20_s0.npz"))
+    assert str(gold["fingerprint"]) == waxman20.fingerprint()
+    r = O.solve(waxman20, O.Options(fixed_iters=1500))
+    L = O.link_loads(waxman20, r.x)
     assert np.all(r.x >= 0)
-    assert np.max((L - config1.capacity) / config1.capacity) <= 1e-9
-    assert np.all(r.S <= config1.demand * (1 + 1e-9))
+    assert np.max((L - waxman20.capacity) / waxman20.capacity) <= 1e-9
+    assert np.all(r.S <= waxman20.demand * (1 + 1e-9))
     assert O.optimality(r.S, gold["S"], 1e-9) >= 0.99
     # bottleneck property: every unsatisfied demand has, on each path, a nearly saturated link
-    unsat = r.S < (1 - 1e-6) * config1.demand
+    unsat = r.S < (1 - 1e-6) * waxman20.demand
     for c in np.nonzero(unsat)[0]:
-        for p in range(config1.demand_path_ptr[c], config1.demand_path_ptr[c + 1]):
-            links = config1.path_links[config1.path_ptr[p]:config1.path_ptr[p + 1]]
-            assert np.max(L[links] / config1.capacity[links]) >= 1 - 1e-3
+        for p in range(waxman20.demand_path_ptr[c], waxman20.demand_path_ptr[c + 1]):
+            links = waxman20.path_links[waxman20.path_ptr[p]:waxman20.path_ptr[p + 1]]
+            assert np.max(L[links] / waxman20.capacity[links]) >= 1 - 1e-3
 
 
-def test_slater_point_feasible(config1):
+def test_slater_point_feasible(waxman20):
     """Appendix C Part I(b): x_r = eps / m_c is strictly feasible for small eps."""
-    m = np.diff(config1.demand_path_ptr)
-    dem_of = np.repeat(np.arange(config1.n_demands), m)
-    kappa = O.link_loads(config1, 1.0 / m[dem_of])
+    m = np.diff(waxman20.demand_path_ptr)
+    dem_of = np.repeat(np.arange(waxman20.n_demands), m)
+    kappa = O.link_loads(waxman20, 1.0 / m[dem_of])
     used = kappa > 0
-    eps = 0.5 * min(config1.demand.min(), np.min(config1.capacity[used] / kappa[used]))
+    eps = 0.5 * min(waxman20.demand.min(), np.min(waxman20.capacity[used] / kappa[used]))
     x = eps / m[dem_of]
-    assert np.all(O.link_loads(config1, x) < config1.capacity)
-    assert np.all(O.demand_sums(config1, x) < config1.demand)
+    assert np.all(O.link_loads(waxman20, x) < waxman20.capacity)
+    assert np.all(O.demand_sums(waxman20, x) < waxman20.demand)
 
 
-def test_schedule_replay_is_exact(config1):
-    a = O.solve(config1, O.Options(fixed_iters=200))
+def test_schedule_replay_is_exact(waxman20):
+    a = O.solve(waxman20, O.Options(fixed_iters=200))
     sb, sa = a.schedule
-    b = O.solve(config1, O.Options(fixed_iters=200, sched_beta=sb, sched_alpha=sa))
+    b = O.solve(waxman20, O.Options(fixed_iters=200, sched_beta=sb, sched_alpha=sa))
     np.testing.assert_array_equal(a.x, b.x)
 
 

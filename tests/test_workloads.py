@@ -43,9 +43,9 @@ def test_yen_matches_brute_force_order(seed):
         assert got == want, (s, t)
 
 
-def test_config1_deterministic_and_shaped():
-    a = W.config1(0)
-    b = W.config1(0)
+def test_waxman20_deterministic_and_shaped():
+    a = W.waxman20(0)
+    b = W.waxman20(0)
     assert a.fingerprint() == b.fingerprint()
     assert a.n_nodes == 20 and a.n_demands == 380
     assert 54 <= a.n_links // 2 <= 66
@@ -61,18 +61,18 @@ def test_config1_deterministic_and_shaped():
         assert np.all(a.link_dst[links[:-1]] == a.link_src[links[1:]])
         nodes = list(a.link_src[links]) + [a.link_dst[links[-1]]]
         assert len(set(nodes)) == len(nodes)
-    assert W.config1(1).fingerprint() != a.fingerprint()
+    assert W.waxman20(1).fingerprint() != a.fingerprint()
 
 
-def test_lambda_star_scaling(config1):
+def test_lambda_star_scaling(waxman20):
     """D = 1.5 * lambda_star * D_gravity: the scaled-down demand 1/1.5 * D is exactly routable."""
-    base = config1.demand / (1.5 * config1.meta["lambda_star"])
-    lam = W.max_concurrent_flow(config1, base)
-    assert lam == pytest.approx(config1.meta["lambda_star"], rel=1e-7)
+    base = waxman20.demand / (1.5 * waxman20.meta["lambda_star"])
+    lam = W.max_concurrent_flow(waxman20, base)
+    assert lam == pytest.approx(waxman20.meta["lambda_star"], rel=1e-7)
 
 
-def test_config4_scenarios_small():
-    sc = W.config4_scenarios(0, n_scen=4)
+def test_failure_scenarios_small():
+    sc = W.failure_scenarios(0, n_scen=4)
     assert len(sc) == 4
     for inst in sc:
         npaths = np.diff(inst.demand_path_ptr)
@@ -80,7 +80,7 @@ def test_config4_scenarios_small():
         cut = inst.meta["cut"]
         assert 1 <= len(cut) <= 3
     assert sc[0].fingerprint() != sc[1].fingerprint()
-    assert W.config4_scenarios(0, n_scen=2)[1].fingerprint() == sc[1].fingerprint()
+    assert W.failure_scenarios(0, n_scen=2)[1].fingerprint() == sc[1].fingerprint()
 
 
 def test_small_builders():

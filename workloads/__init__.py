@@ -344,7 +344,7 @@ def _assemble(name, n, src, dst, cap, pairs, base, paths, factor, meta):
     return inst
 
 
-def config1(seed: int = 0) -> Instance:
+def waxman20(seed: int = 0) -> Instance:
     """20-node Waxman, ~60 links, capacities {10,40,100}, all 380 pairs, lognormal(0,1) gravity,
     1.5x the path-restricted max concurrent flow, k=4 hop-shortest paths."""
     rng = np.random.default_rng(np.random.SeedSequence([1, seed]))
@@ -356,11 +356,11 @@ def config1(seed: int = 0) -> Instance:
     pairs = [(s, t) for s in range(n) for t in range(n) if s != t]
     base = gravity(w, np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs]))
     paths = k_shortest_paths(n, src, dst, np.ones(len(src)), [p[0] for p in pairs], [p[1] for p in pairs], 4)
-    return _assemble(f"config1/s{seed}", n, src, dst, cap, pairs, base, paths, 1.5,
-                     dict(kind="config1", seed=seed, edges=len(edges)))
+    return _assemble(f"waxman20/s{seed}", n, src, dst, cap, pairs, base, paths, 1.5,
+                     dict(kind="waxman20", seed=seed, edges=len(edges)))
 
 
-def config2(seed: int = 0) -> Instance:
+def waxman150(seed: int = 0) -> Instance:
     """150-node Waxman, ~600 links, capacities {100,400}, all 22,350 pairs, lognormal(0,1.5) gravity,
     1.3x the path-restricted max concurrent flow, k=8 Euclidean-latency-shortest paths."""
     rng = np.random.default_rng(np.random.SeedSequence([2, seed]))
@@ -372,11 +372,11 @@ def config2(seed: int = 0) -> Instance:
     pairs = [(s, t) for s in range(n) for t in range(n) if s != t]
     base = gravity(w, np.array([p[0] for p in pairs]), np.array([p[1] for p in pairs]))
     paths = k_shortest_paths(n, src, dst, wgt, [p[0] for p in pairs], [p[1] for p in pairs], 8)
-    return _assemble(f"config2/s{seed}", n, src, dst, cap, pairs, base, paths, 1.3,
-                     dict(kind="config2", seed=seed, edges=len(edges)))
+    return _assemble(f"waxman150/s{seed}", n, src, dst, cap, pairs, base, paths, 1.3,
+                     dict(kind="waxman150", seed=seed, edges=len(edges)))
 
 
-def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_links: int = 80, gateways: int = 4,
+def two_level1000(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_links: int = 80, gateways: int = 4,
             backbone_links: int = 1000, k: int = 4, factor: float = 1.3, cache_dir: str | None = None,
             progress=None) -> Instance:
     """Hierarchical WAN: `regions` Waxman regions of `region_nodes` nodes (~`region_links` links each,
@@ -388,7 +388,7 @@ def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_lin
     max-concurrent-flow LP over ~4M path variables is not tractable here.  Cached as .npz when
     cache_dir is given (the generation runs Yen's algorithm for ~1M pairs)."""
     if cache_dir:
-        path = os.path.join(cache_dir, f"config3_s{seed}.npz")
+        path = os.path.join(cache_dir, f"two_level1000_s{seed}.npz")
         if os.path.exists(path):
             z = np.load(path, allow_pickle=False)
             return Instance(name=str(z["name"]), n_nodes=int(z["n_nodes"]), link_src=z["link_src"],
@@ -435,9 +435,9 @@ def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_lin
     ps, pt = ps[keep], pt[keep]
     base = gravity(w, ps, pt)
     dptr = np.concatenate([[0], np.cumsum(counts[keep])]).astype(np.int32)
-    inst = Instance(name=f"config3/s{seed}", n_nodes=n, link_src=src, link_dst=dst, capacity=cap,
+    inst = Instance(name=f"two_level1000/s{seed}", n_nodes=n, link_src=src, link_dst=dst, capacity=cap,
                     demand_src=ps, demand_dst=pt, demand=base, path_ptr=path_ptr, path_links=path_links,
-                    demand_path_ptr=dptr, meta=dict(kind="config3", seed=seed, edges=len(edges),
+                    demand_path_ptr=dptr, meta=dict(kind="two_level1000", seed=seed, edges=len(edges),
                                                     backbone_edges=len(bb)))
     # uniform-split bound
     m = np.diff(inst.demand_path_ptr)
@@ -451,17 +451,17 @@ def config3(seed: int = 0, regions: int = 50, region_nodes: int = 20, region_lin
     inst.meta.update(lambda_unif=lam, scale_factor=factor, dropped_pairs=int((~keep).sum()))
     if cache_dir:
         os.makedirs(cache_dir, exist_ok=True)
-        np.savez(os.path.join(cache_dir, f"config3_s{seed}.npz"), name=inst.name, n_nodes=inst.n_nodes,
+        np.savez(os.path.join(cache_dir, f"two_level1000_s{seed}.npz"), name=inst.name, n_nodes=inst.n_nodes,
                  link_src=inst.link_src, link_dst=inst.link_dst, capacity=inst.capacity, demand_src=inst.demand_src,
                  demand_dst=inst.demand_dst, demand=inst.demand, path_ptr=inst.path_ptr, path_links=inst.path_links,
                  demand_path_ptr=inst.demand_path_ptr, meta=json.dumps(inst.meta))
     return inst
 
 
-def config4_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
-    """Failure scenarios on the config-1 topology: 1-3 undirected links cut, each demand times
+def failure_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
+    """Failure scenarios on the 20-node topology: 1-3 undirected links cut, each demand times
     exp(N(0, 0.3)), paths recomputed with k_c ~ U{2..8} hop-shortest paths, disconnected pairs dropped."""
-    base = config1(base_seed)
+    base = waxman20(base_seed)
     n = base.n_nodes
     n_edges = base.n_links // 2
     ss = np.random.SeedSequence([4, seed]).spawn(n_scen)
@@ -479,9 +479,9 @@ def config4_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
         kper = rng.integers(2, 9, base.n_demands)
         paths = k_shortest_paths(n, src, dst, np.ones(len(src)), base.demand_src, base.demand_dst, kper)
         keep = [c for c in range(base.n_demands) if len(paths[c]) > 0]
-        inst = make_instance(f"config4/s{seed}/{i}", n, src, dst, cap, base.demand_src[keep],
+        inst = make_instance(f"failures/s{seed}/{i}", n, src, dst, cap, base.demand_src[keep],
                              base.demand_dst[keep], dem[keep], [paths[c] for c in keep],
-                             dict(kind="config4", seed=seed, scenario=i, cut=sorted(cut),
+                             dict(kind="failures", seed=seed, scenario=i, cut=sorted(cut),
                                   dropped_pairs=base.n_demands - len(keep)))
         del remap
         out.append(inst)
