@@ -56,6 +56,22 @@ te_status fail(te_status st, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(TE_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Makes a handle's device current for the duration of an entry point and gives the caller's
+// current device back when the entry point returns.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    err = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+  DeviceScope(const DeviceScope &) = delete;
+  DeviceScope &operator=(const DeviceScope &) = delete;
+};
+
 constexpr int kChunk = 16;                 // iterations per captured graph (even)
 constexpr size_t kMaxBlockLds = 160 * 1024 - 4096;
 
@@ -218,7 +234,8 @@ void normalise(te_ctx *c) {
 }
 
 te_status upload_values(te_ctx *c) {
-  HIPCHK(hipSetDevice(c->device));
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
   HIPCHK(hipMemcpy(c->d_Cn, c->Cn.data(), sizeof(double) * c->E, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->d_Dn, c->Dn.data(), sizeof(double) * c->D, hipMemcpyHostToDevice));
   BatchDesc d{};
@@ -480,7 +497,8 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     te_destroy(c);
     return s;
   };
-  if (hipSetDevice(hip_device) != hipSuccess) return cleanup_fail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
+  DeviceScope dscope(hip_device);
+  if (dscope.err != hipSuccess) return cleanup_fail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
   // index pool: pptr | plinks | dptr | lptr | lpaths
   const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz + c->nnz + c->nzlink.size() +
                     c->nzptr.size() + c->blk.size();
@@ -586,7 +604,8 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   te_status s = check_options(&o);
   if (s != TE_OK) return s;
   hipStream_t stream = (hipStream_t)hip_stream;
-  HIPCHK(hipSetDevice(c->device));
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
   int engine = o.engine;
   if (o.record) {
     if (o.fixed_iters <= 0) return fail(TE_ERR_INVALID, "record = 1 needs fixed_iters > 0");
@@ -730,7 +749,8 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
   te_status s = check_options(&o);
   if (s != TE_OK) return s;
   hipStream_t stream = (hipStream_t)hip_stream;
-  HIPCHK(hipSetDevice(c->device));
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
@@ -769,7 +789,8 @@ te_status te_project(te_ctx *c, void *hip_stream, float *x_out_dev, float *S_out
   if (c->state_scale != c->scale)
     return fail(TE_ERR_STATE, "te_update changed the unit scale since the last solve (continue with warm = 1 first)");
   hipStream_t stream = (hipStream_t)hip_stream;
-  HIPCHK(hipSetDevice(c->device));
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
   HIPCHK(launch_project(c->prob, c->st, c->pb, x_out_dev, S_out_dev, c->scale, 1, stream));
   return TE_OK;
 }
@@ -778,7 +799,8 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   if (!c || !dS_dev || !dC_dev || !dD_dev) return fail(TE_ERR_INVALID, "null handle or buffer");
   if (c->rec_K <= 0) return fail(TE_ERR_STATE, "no recorded solve on this handle (te_solve with record = 1)");
   hipStream_t stream = (hipStream_t)hip_stream;
-  HIPCHK(hipSetDevice(c->device));
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
   const int K = c->rec_K, ck = c->rec_ck;
   const int nck = (K + ck - 1) / ck;
   // the recorded schedule on the host (beta_k, alpha_k, rescale rho_k)
@@ -844,7 +866,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
 
 void te_destroy(te_ctx *c) {
   if (!c) return;
-  (void)hipSetDevice(c->device);
+  DeviceScope dscope(c->device);
   if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
   if (c->rec_chunk) (void)hipGraphExecDestroy(c->rec_chunk);
   for (auto &f : c->ckpt) free_fwd(f);
@@ -935,7 +957,8 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
     te_destroy_batch(b);
     return s;
   };
-  if (hipSetDevice(dev) != hipSuccess) return bail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
+  DeviceScope dscope(dev);
+  if (dscope.err != hipSuccess) return bail(fail(TE_ERR_DEVICE, "hipSetDevice failed"));
   bool ok = dalloc(&b->d_desc, n) == hipSuccess && dalloc(&b->d_out, n) == hipSuccess &&
             dalloc(&b->d_i32, pool.size()) == hipSuccess && dalloc(&b->d_Dn, Dn.size()) == hipSuccess &&
             dalloc(&b->d_Cn, Cn.size()) == hipSuccess && dalloc(&b->d_params, 1) == hipSuccess;
@@ -962,7 +985,8 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
   te_status s = check_options(&o);
   if (s != TE_OK) return s;
   hipStream_t stream = (hipStream_t)hip_stream;
-  HIPCHK(hipSetDevice(b->device));
+  DeviceScope dscope(b->device);
+  HIPCHK(dscope.err);
   Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
   int threads = o.block_threads;
   if (threads == 0) {
@@ -1026,7 +1050,7 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
 
 void te_destroy_batch(te_batch *b) {
   if (!b) return;
-  (void)hipSetDevice(b->device);
+  DeviceScope dscope(b->device);
   void *bufs[] = {b->d_desc, b->d_out, b->d_i32, b->d_Dn, b->d_Cn, b->d_params, b->d_sched};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
