@@ -176,6 +176,23 @@ te_status te_solve(te_ctx *ctx, const te_options *opt, void *hip_stream, const f
 te_status te_project(te_ctx *ctx, void *hip_stream, float *x_out_dev, float *S_out_dev);
 
 /*
+ * Algorithm 2 (section 3.5) applied to caller-supplied path rates under the handle's CURRENT
+ * capacities and demands (those of te_create or the last te_update), with the trim order of the
+ * given alpha.  This is how an allocation computed for an earlier network state is scored under a
+ * later one: the drift-adjusted optimality of section 4.1 applies the rates found at T_0 to the
+ * state at T_K (te_update to T_K, then this call), and the paths keep at most their T_0 rates.
+ *   x_in_dev  [n_paths] float, caller units; read once at the start, so it may alias x_out_dev
+ *   alpha     finite, >= 0: the alpha of the trim scores (the final alpha of the solve that
+ *             produced x_in; any value for rates from elsewhere)
+ *   x_out_dev [n_paths] float, S_out_dev nullable [n_demands] float: caller units, rounded
+ *             toward zero so that the result stays feasible
+ * Stream-ordered; uses the handle's projection buffers (not its solver state, so a warm restart
+ * is unaffected).  TE_ERR_INVALID on a null buffer or a bad alpha.
+ */
+te_status te_project_rates(te_ctx *ctx, void *hip_stream, const float *x_in_dev, double alpha, float *x_out_dev,
+                           float *S_out_dev);
+
+/*
  * Vector-Jacobian product through the last solve run with opt->record = 1 and
  * opt->fixed_iters = K: the unprojected sums S^(K) as a function of capacities
  * and demands, with the recorded (beta, alpha) schedule and the unit scale

@@ -21,7 +21,7 @@ TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
 ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
-       "te_solve_batch", "te_kernel_times", "te_project", "te_destroy", "te_destroy_batch", "te_info",
+       "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_destroy", "te_destroy_batch", "te_info",
        "te_last_error"]
 
 
@@ -84,6 +84,8 @@ def library(path: str = LIB_PATH):
     lib.te_solve_batch.argtypes = [P, ctypes.POINTER(_Options), P, P, P, P]
     lib.te_project.restype = I
     lib.te_project.argtypes = [P, P, P, P]
+    lib.te_project_rates.restype = I
+    lib.te_project_rates.argtypes = [P, P, P, ctypes.c_double, P, P]
     lib.te_kernel_times.restype = I
     lib.te_kernel_times.argtypes = [P, ctypes.POINTER(_Options), P, I, P]
     lib.te_destroy.restype = None
@@ -250,6 +252,24 @@ class Problem:
             S_out = torch.empty(self.n_demands, dtype=torch.float32, device=dev)
         sp = _stream_ptr(dev) if stream is None else stream
         _check(library().te_project(self._h, sp, x_out.data_ptr(), S_out.data_ptr()))
+        return x_out, S_out
+
+    def project_rates(self, x, alpha, x_out=None, S_out=None, stream=None):
+        """Algorithm 2 applied to the given path rates x (caller units) under the handle's current
+        capacities and demands, with trim scores at `alpha` (te_project_rates): returns (x [n_paths],
+        S [n_demands]) float32 cuda tensors in caller units."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        x = torch.as_tensor(x).to(device=dev, dtype=torch.float32).contiguous()
+        if x.numel() != self.n_paths:
+            raise ValueError(f"x has {x.numel()} entries, the instance has {self.n_paths} paths")
+        if x_out is None:
+            x_out = torch.empty(self.n_paths, dtype=torch.float32, device=dev)
+        if S_out is None:
+            S_out = torch.empty(self.n_demands, dtype=torch.float32, device=dev)
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_project_rates(self._h, sp, x.data_ptr(), float(alpha), x_out.data_ptr(),
+                                          S_out.data_ptr()))
         return x_out, S_out
 
     def kernel_times(self, opts: Options | None = None, iters: int = 64, stream=None):

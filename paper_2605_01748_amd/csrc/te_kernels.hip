@@ -429,6 +429,22 @@ __global__ void kp_clamp_sums(Prob p, State s, ProjBuf b) {
   }
 }
 
+// step 1 on caller rates (caller units): clamp into the working copy in normalised units
+__global__ void kp_clamp_sums_in(Prob p, const float *x_in, double scale, ProjBuf b) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    double sum = 0.0;
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      const double v = fmax((double)x_in[r] / scale, 0.0);
+      b.xd[r] = v;
+      sum += v;
+      b.trim[r] = 0ull;
+    }
+    b.S[c] = sum;
+  }
+}
+
 __global__ void kp_loads(Prob p, ProjBuf b) {
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   const int nw = (gridDim.x * blockDim.x) >> 6;
@@ -441,8 +457,9 @@ __global__ void kp_loads(Prob p, ProjBuf b) {
 }
 
 // C_p = number of violated links on p, and the log score
-__global__ void kp_counts(Prob p, ProjBuf b, const Ctrl *fin) {
-  const float alpha = (float)fin->alpha;
+// alpha of the scores: the solve's final alpha (fin) or, with fin null, the given one
+__global__ void kp_counts(Prob p, ProjBuf b, const Ctrl *fin, double alpha_in) {
+  const float alpha = (float)(fin ? fin->alpha : alpha_in);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
@@ -1133,21 +1150,36 @@ hipError_t launch_finish(const State &s, const Params *prm, int last_par, hipStr
   return hipGetLastError();
 }
 
+// steps 2-5 of Algorithm 2 on the clamped working copy b.xd / b.S
+static void launch_trims(const Prob &p, const ProjBuf &b, const Ctrl *fin, double alpha, hipStream_t st) {
+  const int nD = (p.D + 255) / 256, nE = (p.E * 64 + 255) / 256;
+  hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
+  hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin, alpha);
+  hipLaunchKernelGGL(kp_demand_trim, dim3(nD), dim3(256), 0, st, p, b);
+  hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
+  hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin, alpha);
+  int nl = p.E < 4096 ? p.E : 4096;
+  hipLaunchKernelGGL(kp_link_trim, dim3(nl > 0 ? nl : 1), dim3(256), 0, st, p, b);
+}
+
 hipError_t launch_project(const Prob &p, const State &s, const ProjBuf &b, float *x_out, float *S_out,
                           double scale, int project, hipStream_t st) {
-  const Ctrl *fin = s.ctrl + 2;
-  const int nD = (p.D + 255) / 256, nE = (p.E * 64 + 255) / 256;
+  const int nD = (p.D + 255) / 256;
   if (project) {
     hipLaunchKernelGGL(kp_clamp_sums, dim3(nD), dim3(256), 0, st, p, s, b);
-    hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
-    hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin);
-    hipLaunchKernelGGL(kp_demand_trim, dim3(nD), dim3(256), 0, st, p, b);
-    hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
-    hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin);
-    int nl = p.E < 4096 ? p.E : 4096;
-    hipLaunchKernelGGL(kp_link_trim, dim3(nl > 0 ? nl : 1), dim3(256), 0, st, p, b);
+    launch_trims(p, b, s.ctrl + 2, 0.0, st);
   }
   hipLaunchKernelGGL(kp_output, dim3(nD), dim3(256), 0, st, p, b, x_out, S_out, scale, project, s.x);
+  return hipGetLastError();
+}
+
+// Algorithm 2 on caller rates x_in (caller units) at the given alpha; x_out may alias x_in
+hipError_t launch_project_rates(const Prob &p, const ProjBuf &b, const float *x_in, double alpha, float *x_out,
+                                float *S_out, double scale, hipStream_t st) {
+  const int nD = (p.D + 255) / 256;
+  hipLaunchKernelGGL(kp_clamp_sums_in, dim3(nD), dim3(256), 0, st, p, x_in, scale, b);
+  launch_trims(p, b, nullptr, alpha, st);
+  hipLaunchKernelGGL(kp_output, dim3(nD), dim3(256), 0, st, p, b, x_out, S_out, scale, 1, (const double *)nullptr);
   return hipGetLastError();
 }
 

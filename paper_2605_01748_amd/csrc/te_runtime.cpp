@@ -25,6 +25,8 @@ hipError_t launch_demand_timed(const Prob &, const State &, const Params *, int,
 hipError_t launch_link_timed(const Prob &, const State &, const Params *, int, hipStream_t, hipEvent_t, hipEvent_t);
 hipError_t launch_finish(const State &, const Params *, int, hipStream_t);
 hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *, float *, double, int, hipStream_t);
+hipError_t launch_project_rates(const Prob &, const ProjBuf &, const float *, double, float *, float *, double,
+                                hipStream_t);
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
                               BatchOut *, size_t, int, hipStream_t);
 size_t block_lds_bytes(int E, int P, int D, int nnz);
@@ -792,6 +794,17 @@ te_status te_project(te_ctx *c, void *hip_stream, float *x_out_dev, float *S_out
   DeviceScope dscope(c->device);
   HIPCHK(dscope.err);
   HIPCHK(launch_project(c->prob, c->st, c->pb, x_out_dev, S_out_dev, c->scale, 1, stream));
+  return TE_OK;
+}
+
+te_status te_project_rates(te_ctx *c, void *hip_stream, const float *x_in_dev, double alpha, float *x_out_dev,
+                           float *S_out_dev) {
+  if (!c || !x_in_dev || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or buffer");
+  if (!std::isfinite(alpha) || alpha < 0.0) return fail(TE_ERR_INVALID, "alpha must be finite and >= 0");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
+  HIPCHK(launch_project_rates(c->prob, c->pb, x_in_dev, alpha, x_out_dev, S_out_dev, c->scale, stream));
   return TE_OK;
 }
 

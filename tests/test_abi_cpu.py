@@ -105,3 +105,15 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[f"{name} size"]) == ctypes.sizeof(cls), name
         for f, _ in cls._fields_:
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def test_dao_optimality_metric():
+    """Section 4.1's optimality: mean over demands of min(X_d / max(OPT_d, theta), 1) -- rates above
+    the optimum are not rewarded, theta guards zero optima."""
+    from paper_2605_01748_amd import dao
+    assert dao.optimality([1.0, 2.0], [1.0, 2.0], 1e-9) == 1.0
+    assert dao.optimality([0.5, 4.0], [1.0, 2.0], 1e-9) == 0.75
+    assert dao.optimality([0.0, 0.0], [1.0, 0.0], 1e-9) == 0.0
+    assert dao.optimality([1e-10], [0.0], 1e-9) == pytest.approx(0.1)
+    with pytest.raises(ValueError):
+        dao.optimality([1.0], [1.0, 2.0], 1e-9)

@@ -337,6 +337,41 @@ def test_projection_invariants_random(waxman20):
     assert np.all(xp <= np.maximum(x, 0) + 1e-15)
 
 
+def test_projection_under_demand_drift_closed_form(waxman20):
+    """Rates that fit the capacities, applied under drifted demands with unchanged capacities (the
+    drift-adjusted optimality of section 4.1): only demand trims act, so every demand gets exactly
+    min(S_c, D_c') and no path rises."""
+    r = O.solve(waxman20, O.Options(fixed_iters=400))
+    later = W.drift_path(waxman20, [300.0], seed=2, cap_events_per_day=0.0)[0]
+    assert np.any(later.demand < r.S) and np.any(later.demand > r.S)
+    xa = O.project(later, r.x, 2.0)
+    np.testing.assert_allclose(O.demand_sums(later, xa), np.minimum(r.S, later.demand), rtol=1e-12, atol=1e-15)
+    assert np.all(xa <= r.x)
+
+
+def test_projection_under_capacity_cut(waxman20):
+    """The same rates after one link's capacity is halved: feasible, no demand gains, and the
+    demands none of whose paths cross an over-full link keep their rates (up to the last-bit
+    demand trims of rates whose sum rounds above the demand)."""
+    r = O.solve(waxman20, O.Options(fixed_iters=400))
+    L = O.link_loads(waxman20, r.x)
+    e = int(np.argmax(L))
+    cap = waxman20.capacity.copy()
+    cap[e] *= 0.5
+    later = W.Instance(**{**waxman20.__dict__, "capacity": cap})
+    xa = O.project(later, r.x, 2.0)
+    Sa = O.demand_sums(later, xa)
+    assert np.all(O.link_loads(later, xa) <= cap * (1 + 1e-12))
+    assert np.all(Sa <= r.S * (1 + 1e-15))
+    over = O.link_loads(later, r.x) > cap
+    S0 = O.demand_sums(waxman20, r.x)
+    for c in range(waxman20.n_demands):
+        ps = range(waxman20.demand_path_ptr[c], waxman20.demand_path_ptr[c + 1])
+        if not any(over[waxman20.path_links[waxman20.path_ptr[p]:waxman20.path_ptr[p + 1]]].any() for p in ps):
+            assert abs(Sa[c] - S0[c]) <= 1e-14 * S0[c]
+    assert Sa.sum() < r.S.sum()
+
+
 # ------------------------------------------------------------------------------------------
 # whole-solve invariants and identities
 # ------------------------------------------------------------------------------------------

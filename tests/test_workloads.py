@@ -90,3 +90,58 @@ def test_small_builders():
     assert sl.n_links == 1 and sl.nnz == 2
     pp = W.parallel_paths([0.2, 0.3], 1.0)
     assert pp.n_paths == 2
+
+
+def test_swing_sigma_calibration():
+    """The lognormal ratio exp(sigma Z - sigma^2 / 2) has mean 1 and mean absolute change `swing`
+    (checked by quadrature of the normal density, independent of the closed form)."""
+    from scipy import integrate
+    for swing in (0.0, 0.1, 0.35, 1.0):
+        s = W.swing_sigma(swing)
+        dens = lambda z: np.exp(-0.5 * z * z) / np.sqrt(2 * np.pi)  # noqa: E731
+        mean = integrate.quad(lambda z: np.exp(s * z - 0.5 * s * s) * dens(z), -40, 40)[0]
+        mad = integrate.quad(lambda z: abs(np.exp(s * z - 0.5 * s * s) - 1.0) * dens(z), -40, 40, points=[s / 2])[0]
+        assert abs(mean - 1.0) < 1e-9
+        assert abs(mad - swing) < 1e-9
+    with pytest.raises(ValueError):
+        W.swing_sigma(2.5)
+
+
+def test_drift_path_statistics(waxman20):
+    """Demands: unchanged at t = 0, mean absolute change ~35 % after five minutes, log-variance
+    growing linearly in time, mean preserved.  Capacities: only links with capacity change, each to
+    a fraction in [0.25, 1] of its initial value; topology and paths untouched."""
+    base = waxman20
+    # many independent demands: replicate the instance's demand vector
+    big = W.Instance(name="rep", n_nodes=base.n_nodes, link_src=base.link_src, link_dst=base.link_dst,
+                     capacity=base.capacity, demand_src=np.zeros(40000, np.int32), demand_dst=np.ones(40000, np.int32),
+                     demand=np.ones(40000), path_ptr=base.path_ptr, path_links=base.path_links,
+                     demand_path_ptr=base.demand_path_ptr)
+    st = W.drift_path(big, [0.0, 75.0, 300.0, 1200.0], seed=4, cap_events_per_day=86400 * 0.05)
+    np.testing.assert_array_equal(st[0].demand, big.demand)
+    np.testing.assert_array_equal(st[0].capacity, big.capacity)
+    r300 = st[2].demand
+    assert abs(np.mean(np.abs(r300 - 1.0)) - 0.35) < 0.01
+    assert abs(np.mean(r300) - 1.0) < 0.01
+    sig2 = W.swing_sigma() ** 2
+    for s, t in zip(st[1:], (75.0, 300.0, 1200.0)):
+        assert abs(np.var(np.log(s.demand)) / (sig2 * t / 300.0) - 1.0) < 0.05
+        assert np.all(s.demand > 0) and np.all(np.isfinite(s.demand))
+        ratio = s.capacity / big.capacity
+        changed = ratio != 1.0
+        assert np.all((ratio[changed] >= 0.25) & (ratio[changed] <= 1.0))
+        assert s.path_links is big.path_links and s.demand_path_ptr is big.demand_path_ptr
+    assert st[-1].meta["drift"]["cap_events"] > 0
+    # the same call gives the same path
+    again = W.drift_path(big, [0.0, 75.0, 300.0, 1200.0], seed=4, cap_events_per_day=86400 * 0.05)
+    np.testing.assert_array_equal(again[3].demand, st[3].demand)
+    np.testing.assert_array_equal(again[3].capacity, st[3].capacity)
+    with pytest.raises(ValueError):
+        W.drift_path(big, [1.0, 0.5])
+
+
+def test_drift_path_keeps_unused_links_at_zero():
+    inst = W.ragged(0)
+    s = W.drift_path(inst, [3600.0], seed=1, cap_events_per_day=86400.0)[0]
+    assert np.all(s.capacity[inst.capacity == 0.0] == 0.0)
+    assert s.meta["drift"]["cap_events"] > 0

@@ -21,6 +21,9 @@ Recipes (all seeded through ``numpy.random.SeedSequence``):
   graph).
 * Paths: the first k simple paths in (cost, node sequence) order, cost = hop
   count or Euclidean length (Yen's algorithm, ``ksp.c``).
+* Drift (``drift_path``): demands follow mean-preserving geometric Brownian motions calibrated to
+  a 35 % mean absolute change per five minutes; link capacities change at Poisson times (200 per
+  day over the network), each to U(0.25, 1) of its initial value.
 * Scale: D = factor * lambda_star * D_gravity, where lambda_star is the largest
   lambda for which lambda * D_gravity is routable on the given paths (max
   concurrent flow, one LP).  The tightest path-restricted cut is then
@@ -485,6 +488,69 @@ def failure_scenarios(seed: int = 0, n_scen: int = 512, base_seed: int = 0):
                                   dropped_pairs=base.n_demands - len(keep)))
         del remap
         out.append(inst)
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# synthetic drift of the network state over time (drift-adjusted optimality, section 4.1)
+# ----------------------------------------------------------------------------------------------
+SWING_5MIN = 0.35  # mean absolute relative demand change over five minutes (section 2, after prior work)
+CAP_EVENTS_PER_DAY = 200.0  # link-capacity changes per day over the whole network (section 2: "O(100s)")
+
+
+def swing_sigma(swing: float = SWING_5MIN) -> float:
+    """Volatility per period of the mean-preserving lognormal ratio Y = exp(sigma Z - sigma^2 / 2)
+    whose mean absolute change E|Y - 1| equals `swing`.  Since E[Y] = 1, E|Y - 1| = 2 E[(Y - 1)+]
+    = 2 (2 Phi(sigma / 2) - 1), so sigma = 2 Phi^-1((1 + swing / 2) / 2)."""
+    from scipy.stats import norm
+    if not 0.0 <= swing < 2.0:
+        raise ValueError("swing must be in [0, 2)")
+    return float(2.0 * norm.ppf((1.0 + 0.5 * swing) / 2.0))
+
+
+def drift_path(inst: Instance, times, seed: int = 0, swing: float = SWING_5MIN, period: float = 300.0,
+               cap_events_per_day: float = CAP_EVENTS_PER_DAY, cap_low: float = 0.25):
+    """Network states at `times` (seconds after T_0, sorted, >= 0) along ONE seeded sample path, as
+    Instances with the topology and paths of `inst` and drifted capacities and demands.
+
+    * Demands: independent geometric Brownian motions without drift in the mean,
+      D_c(t) = D_c(0) exp(sigma W_c(t / period) - sigma^2 t / (2 period)), with sigma = swing_sigma(swing),
+      so that the mean absolute change over one period is `swing` and E[D_c(t)] = D_c(0).
+    * Capacities: capacity-change events arrive as a Poisson process of rate cap_events_per_day / 86400
+      per second over the whole network, each on a uniformly drawn link with nonzero capacity, which
+      is set to its T_0 capacity times U(cap_low, 1) (a degradation, or a partial recovery).
+    States at later times extend the same path, so a state at T_K is the drift of the state at any
+    earlier grid time."""
+    times = np.asarray(times, dtype=np.float64)
+    if times.ndim != 1 or np.any(times < 0.0) or np.any(np.diff(times) < 0.0):
+        raise ValueError("times must be a sorted 1-D array of non-negative seconds")
+    rng = np.random.default_rng(np.random.SeedSequence([11, seed]))
+    sigma = swing_sigma(swing)
+    D, E = inst.n_demands, inst.n_links
+    t_end = float(times[-1]) if times.size else 0.0
+    n_ev = int(rng.poisson(cap_events_per_day / 86400.0 * t_end)) if t_end > 0.0 else 0
+    ev_t = np.sort(rng.uniform(0.0, t_end, n_ev)) if n_ev else np.zeros(0)
+    live = np.flatnonzero(inst.capacity > 0.0)
+    ev_link = rng.choice(live, size=n_ev) if n_ev else np.zeros(0, np.int64)
+    ev_f = rng.uniform(cap_low, 1.0, n_ev)
+    logw = np.zeros(D)
+    t_prev = 0.0
+    out = []
+    for t in times:
+        dt = (t - t_prev) / period
+        if dt > 0.0:
+            logw += np.sqrt(dt) * rng.standard_normal(D)
+        t_prev = t
+        demand = inst.demand * np.exp(sigma * logw - 0.5 * sigma * sigma * t / period)
+        cap = inst.capacity.copy()
+        for j in range(int(np.searchsorted(ev_t, t, side="right"))):
+            cap[ev_link[j]] = inst.capacity[ev_link[j]] * ev_f[j]
+        meta = dict(inst.meta, drift=dict(seed=seed, t=float(t), swing=swing, period=period,
+                                          cap_events=int(np.searchsorted(ev_t, t, side="right"))))
+        out.append(Instance(name=f"{inst.name}@{float(t):g}s", n_nodes=inst.n_nodes, link_src=inst.link_src,
+                            link_dst=inst.link_dst, capacity=cap, demand_src=inst.demand_src,
+                            demand_dst=inst.demand_dst, demand=demand, path_ptr=inst.path_ptr,
+                            path_links=inst.path_links, demand_path_ptr=inst.demand_path_ptr, meta=meta))
     return out
 
 
