@@ -64,3 +64,16 @@ def test_definition_no_commodity_can_rise(which):
         lower[c] = 0.0
         best = _max_single(inst, c, lower)
         assert best <= S[c] * (1 + 1e-6) + 1e-9, (c, best, S[c])
+
+
+def test_drift_golden_matches_generator():
+    """The stored exact max-min allocations of the drifted 150-node states belong to the states the
+    generator produces (same fingerprints), one rate per demand within its demand."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "maxmin_waxman150_drift_s0.npz"))
+    states = W.drift_path(W.waxman150(0), [float(t) for t in g["t"]], seed=0)
+    for i, s in enumerate(states):
+        assert str(g[f"fp{i}"]) == s.fingerprint()
+        S = g[f"S{i}"]
+        assert S.shape == (s.n_demands,)
+        assert np.all(S >= 0) and np.all(S <= s.demand * (1 + 1e-9))
