@@ -96,6 +96,11 @@ typedef struct {
   int32_t block_threads; /* workgroup engine: threads per workgroup, 256, 512 or 1024; 0 (default):
                             1024 for single solves, and for batches the fastest of the three measured
                             on the batch's first solve (kept by the batch handle) */
+  int32_t paths_per_lane; /* workgroup engine: paths of a demand held by one lane in the demand step,
+                            1, 2, 4 or 8 (a demand with G path slots gets max(1, G / paths_per_lane)
+                            lanes); 0 (default): 1 for single solves, and for batches the fastest
+                            pair (block_threads, paths_per_lane) measured on the batch's first solve
+                            when both are 0 */
   int32_t warm;        /* 1: continue from the state the handle's last graph-engine solve left (rates,
                           every dual, beta and alpha; alpha capped at alpha_target) instead of
                           initialising, e.g. after te_update; the iteration count restarts at 0.
@@ -115,6 +120,7 @@ typedef struct {
   int32_t stop_iter;   /* first iteration at which the stop test passed, -1 if never */
   int32_t engine;      /* engine that ran */
   int32_t block_threads; /* workgroup engine: threads per workgroup that ran (0 for the graph engine) */
+  int32_t paths_per_lane; /* workgroup engine: paths per lane that ran (0 for the graph engine) */
   double final_alpha;
   double beta;         /* final penalty */
   double r, s;         /* last primal and dual residuals (section 3.4) */

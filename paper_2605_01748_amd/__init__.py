@@ -37,13 +37,15 @@ class _Options(ctypes.Structure):
                 ("beta_max", ctypes.c_double), ("max_iters", ctypes.c_int32), ("alpha_max", ctypes.c_int32),
                 ("fixed_iters", ctypes.c_int32), ("adapt_beta", ctypes.c_int32), ("beta_every", ctypes.c_int32),
                 ("project", ctypes.c_int32), ("engine", ctypes.c_int32), ("record", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("warm", ctypes.c_int32), ("sched_beta", ctypes.c_void_p),
+                ("ckpt_every", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("paths_per_lane", ctypes.c_int32), ("warm", ctypes.c_int32), ("sched_beta", ctypes.c_void_p),
                 ("sched_alpha", ctypes.c_void_p), ("sched_len", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("flags", ctypes.c_int32), ("stop_iter", ctypes.c_int32),
-                ("engine", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("final_alpha", ctypes.c_double),
+                ("engine", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("paths_per_lane", ctypes.c_int32), ("final_alpha", ctypes.c_double),
                 ("beta", ctypes.c_double),
                 ("r", ctypes.c_double), ("s", ctypes.c_double), ("max_cap_viol_rel", ctypes.c_double),
                 ("max_dem_viol_rel", ctypes.c_double), ("ms", ctypes.c_double)]
@@ -124,6 +126,7 @@ class Options:
     record: bool = False
     ckpt_every: int = 16
     block_threads: int = 0             # workgroup engine: 256, 512, 1024; 0 = default / tuned for batches
+    paths_per_lane: int = 0            # workgroup engine: 1, 2, 4, 8; 0 = default / tuned for batches
     warm: bool = False                 # continue from the handle's last graph-engine state
     sched_beta: np.ndarray | None = None
     sched_alpha: np.ndarray | None = None
@@ -148,6 +151,7 @@ class Options:
         o.record = int(self.record)
         o.ckpt_every = self.ckpt_every
         o.block_threads = self.block_threads
+        o.paths_per_lane = self.paths_per_lane
         o.warm = int(self.warm)
         keep = []
         if self.sched_beta is not None:

@@ -105,6 +105,15 @@ struct Lane {
   bool on;      // lane holds a path of the demand
 };
 
+// A lane holding up to PPL paths of one demand (slot j: path lane + j * (lanes per demand) of the
+// demand's list; bit j of `on` set if that path exists).  The per-demand work of the root solve is
+// then shared by fewer lanes per demand, and PPL = 1 is the one-path lane above.
+template <int PPL>
+struct LaneN {
+  double a[PPL], un[PPL], n[PPL], rn[PPL], rn1[PPL];
+  unsigned on;
+};
+
 struct Dem {
   double D, u, binv;  // demand, u_dem (current scale), 1/beta
   double alpha;
@@ -161,6 +170,33 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
   dF = -dh * dv - 1.0;
 }
 
+template <int PPL>
+__device__ __forceinline__ void F_eval(double S, const LaneN<PPL> &L, const Dem &c, int G, double &F, double &dF) {
+  if (c.alpha > 0.0 && !(S > 0.0)) {
+    F = INFINITY;
+    dF = -INFINITY;
+    return;
+  }
+  const double t = S - c.D + c.u;
+  const double invS = c.alpha > 0.0 ? 1.0 / S : 0.0;
+  const double pw = pow_neg_alpha(S, invS, c.alpha);
+  const double h = fmax(t, 0.0) - pw * c.binv;
+  const double dh = (t > 0.0 ? 1.0 : 0.0) + (c.alpha > 0.0 ? c.alpha * pw * c.binv * invS : 0.0);
+  double v = 0.0, dv = 0.0;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    if (!((L.on >> j) & 1u)) continue;
+    const double b = L.a[j] - h;
+    const bool hi_branch = b >= L.n[j] * L.un[j];
+    v += hi_branch ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
+    dv += hi_branch ? L.rn[j] : L.rn1[j];
+  }
+  v = group_sum_d(v, G);
+  dv = group_sum_d(dv, G);
+  F = v - S;
+  dF = -dh * dv - 1.0;
+}
+
 // Safeguarded Newton (appendix B.2) from the warm start S0: every evaluation narrows the bracket
 // [lo, hi] with F(lo) > 0 > F(hi) (ends infinite until a sign of each kind has been seen); the next
 // point is the Newton point when it lies strictly inside the bracket (and stays positive for
@@ -168,7 +204,8 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
 // halving towards 0 for alpha > 0).  Stops when the Newton correction or the bracket falls below
 // 1e-13 max(1, |S|) (normalised units, where F's rounding noise is ~1e-16 of its O(1) terms).
 // Mean cost on the 150-node instance: 2.1 evaluations of F per demand and iteration.
-__device__ double sum_root(double S, const Lane &L, const Dem &c, int G, int *evals) {
+template <class LaneT>
+__device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *evals) {
   const double tol = 1e-13;
   if (c.alpha > 0.0 && !(S > 0.0)) S = fmax(c.D, 1e-6);
   double lo = -INFINITY, hi = INFINITY, expand = 0.0;

@@ -669,7 +669,10 @@ __global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double 
 // ------------------------------------------------------------------------------------------
 // Workgroup engine: the whole solve of one instance inside one workgroup, state in LDS.
 // ------------------------------------------------------------------------------------------
-template <int NT>
+// PPL: paths per lane in the demand step.  A demand with G path slots gets G / PPL lanes (at least
+// one), each holding up to PPL of its paths; fewer lanes per demand share the per-demand work of the
+// root solve (bracket, Newton step, S^-alpha) between fewer lanes and need fewer group sums.
+template <int NT, int PPL>
 __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pools pools,
                                                                const Params *prmp, int project, float *x_out,
                                                                float *S_out, BatchOut *outs) {
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
   __shared__ Ctrl cs;
   __shared__ double red[4][16];
   const BatchDesc d = descs[blockIdx.x];
-  const int E = d.E, P = d.P, D = d.D, nnz = d.nnz, G = d.G, logG = d.logG;
+  const int E = d.E, P = d.P, D = d.D, nnz = d.nnz, logG = d.logG;
   // LDS layout
   double2 *gq = (double2 *)smem;                     // E
   double *Cn = (double *)(gq + E);                   // E
@@ -728,8 +731,11 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
   if (tid == 0) cs = initial_ctrl(prm);
   __syncthreads();
 
-  const int lane = tid & (G - 1);
-  const int groups = nth >> logG;
+  constexpr int kLogPPL = PPL >= 8 ? 3 : PPL >= 4 ? 2 : PPL >= 2 ? 1 : 0;
+  const int logGp = logG > kLogPPL ? logG - kLogPPL : 0;  // lanes per demand: Gp = G / PPL, at least 1
+  const int Gp = 1 << logGp;
+  const int lane = tid & (Gp - 1);
+  const int groups = nth >> logGp;
   const int w = tid >> 6, l64 = tid & 63, nw = nth >> 6;
   // this wavefront's part of the CSC entries for the link step, and the rank (among non-empty
   // links) of the link holding its first entry
@@ -758,46 +764,56 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
     double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY, cap_v = -INFINITY;
     // demand step
     for (int c0 = 0; c0 < D; c0 += groups) {
-      const int c = c0 + (tid >> logG);
+      const int c = c0 + (tid >> logGp);
       if (c < D) {
         const int r0 = dptr[c], np = dptr[c + 1] - r0;
-        Lane L;
-        L.on = lane < np;
-        const int r = r0 + (L.on ? lane : 0);
-        double xr = 0.0;
-        int n = 1;
-        L.a = 0.0;
-        L.un = 0.0;
-        if (L.on) {
-          const int i0 = pptr[r], i1 = pptr[r + 1];
-          n = i1 - i0;
-          double sg = 0.0, sq = 0.0;
-          for (int i = i0; i < i1; ++i) {
-            const double2 v = gq[plinks[i]];
-            sg += v.x;
-            sq += v.y;
+        LaneN<PPL> L;
+        L.on = 0u;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          const int idx = lane + j * Gp;
+          int n = 1;
+          L.a[j] = 0.0;
+          L.un[j] = 0.0;
+          if (idx < np) {
+            const int r = r0 + idx;
+            const int i0 = pptr[r], i1 = pptr[r + 1];
+            n = i1 - i0;
+            double sg = 0.0, sq = 0.0;
+            for (int i = i0; i < i1; ++i) {
+              const double2 v = gq[plinks[i]];
+              sg += v.x;
+              sq += v.y;
+            }
+            L.a[j] = (double)n * x[r] - (sg * inv_f - sq);
+            L.un[j] = uneg[r] * inv_f;
+            L.on |= 1u << j;
           }
-          xr = x[r];
-          L.a = (double)n * xr - (sg * inv_f - sq);
-          L.un = uneg[r] * inv_f;
+          L.n[j] = (double)n;
+          L.rn[j] = 1.0 / (double)n;
+          L.rn1[j] = 1.0 / (double)(n + 1);
         }
-        L.n = (double)n;
-        L.rn = 1.0 / (double)n;
-        L.rn1 = 1.0 / (double)(n + 1);
         dm.D = Dn[c];
         dm.u = udem[c] * inv_f;
         int steps;
-        const double Sst = sum_root(S[c], L, dm, G, &steps);
+        const double Sst = sum_root(S[c], L, dm, Gp, &steps);
         const double h = h_of(Sst, dm);
-        const double xn = L.on ? xi_of(L.a - h, L) : 0.0;
-        const double Ssum = group_sum_d(xn, G);
-        if (L.on) {
-          const double un = fmax(L.un - xn, 0.0);
+        double xsum = 0.0;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+          if (!((L.on >> j) & 1u)) continue;
+          const int r = r0 + lane + j * Gp;
+          const double b = L.a[j] - h;
+          const double xn = (b >= L.n[j] * L.un[j]) ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
+          const double xr = x[r];
+          const double un = fmax(L.un[j] - xn, 0.0);
           x[r] = xn;
           uneg[r] = un;
+          xsum += xn;
           ds2 += (xn - xr) * (xn - xr);
-          dr2 += (un - L.un) * (un - L.un);
+          dr2 += (un - L.un[j]) * (un - L.un[j]);
         }
+        const double Ssum = group_sum_d(xsum, Gp);
         if (lane == 0) {
           const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
           udem[c] = ud;
@@ -1183,25 +1199,37 @@ hipError_t launch_project_rates(const Prob &p, const ProjBuf &b, const float *x_
   return hipGetLastError();
 }
 
-template <int NT>
+template <int NT, int PPL>
 hipError_t launch_block_nt(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
                            float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, hipStream_t st) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_block_solve<NT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds_bytes);
+  hipError_t e = hipFuncSetAttribute((const void *)k_block_solve<NT, PPL>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_block_solve<NT>, dim3(n), dim3(NT), lds_bytes, st, descs, pools, prm, project, x_out, S_out,
-                     outs);
+  hipLaunchKernelGGL((k_block_solve<NT, PPL>), dim3(n), dim3(NT), lds_bytes, st, descs, pools, prm, project, x_out,
+                     S_out, outs);
   return hipGetLastError();
 }
 
-// threads: 256, 512 or 1024 per workgroup (one instance per workgroup)
+template <int NT>
+hipError_t launch_block_ppl(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
+                            float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, int ppl, hipStream_t st) {
+  switch (ppl) {
+    case 1: return launch_block_nt<NT, 1>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 2: return launch_block_nt<NT, 2>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 4: return launch_block_nt<NT, 4>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 8: return launch_block_nt<NT, 8>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// threads: 256, 512 or 1024 per workgroup (one instance per workgroup); ppl: paths per lane, 1, 2, 4 or 8
 hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools, const Params *prm, int project,
-                              float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, int threads,
+                              float *x_out, float *S_out, BatchOut *outs, size_t lds_bytes, int threads, int ppl,
                               hipStream_t st) {
   switch (threads) {
-    case 256: return launch_block_nt<256>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
-    case 512: return launch_block_nt<512>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
-    case 1024: return launch_block_nt<1024>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, st);
+    case 256: return launch_block_ppl<256>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, ppl, st);
+    case 512: return launch_block_ppl<512>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, ppl, st);
+    case 1024: return launch_block_ppl<1024>(descs, n, pools, prm, project, x_out, S_out, outs, lds_bytes, ppl, st);
     default: return hipErrorInvalidValue;
   }
 }

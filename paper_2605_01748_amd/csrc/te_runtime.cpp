@@ -5,6 +5,8 @@
 // the graph engine as captured HIP graphs of fixed-length iteration chunks, and runs the
 // workgroup engine for small instances and batches.
 #include <hip/hip_runtime.h>
+#include <map>
+#include <utility>
 
 #include <algorithm>
 #include <cmath>
@@ -28,7 +30,7 @@ hipError_t launch_project(const Prob &, const State &, const ProjBuf &, float *,
 hipError_t launch_project_rates(const Prob &, const ProjBuf &, const float *, double, float *, float *, double,
                                 hipStream_t);
 hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Params *, int, float *, float *,
-                              BatchOut *, size_t, int, hipStream_t);
+                              BatchOut *, size_t, int, int, hipStream_t);
 size_t block_lds_bytes(int E, int P, int D, int nnz);
 hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStream_t);
 hipError_t launch_adj_iteration(const Prob &, int, int, const FwdState &, const FwdState &, const AdjState &, double,
@@ -150,7 +152,9 @@ struct te_batch {
   int64_t totP = 0, totD = 0;
   std::vector<double> scales;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  int32_t tuned_threads = 0;  // workgroup size picked on the first solve with block_threads = 0
+  // (block_threads, paths_per_lane) picked on the first solve that leaves one or both at 0, per
+  // requested pair
+  std::map<std::pair<int, int>, std::pair<int, int>> tuned;
 };
 
 extern "C" {
@@ -306,6 +310,9 @@ te_status check_options(const te_options *o) {
   if (o->sched_len < 0) return fail(TE_ERR_INVALID, "sched_len < 0");
   if (o->block_threads != 0 && o->block_threads != 256 && o->block_threads != 512 && o->block_threads != 1024)
     return fail(TE_ERR_INVALID, "block_threads must be 0, 256, 512 or 1024");
+  if (o->paths_per_lane != 0 && o->paths_per_lane != 1 && o->paths_per_lane != 2 && o->paths_per_lane != 4 &&
+      o->paths_per_lane != 8)
+    return fail(TE_ERR_INVALID, "paths_per_lane must be 0, 1, 2, 4 or 8");
   return TE_OK;
 }
 
@@ -379,12 +386,13 @@ hipError_t copy_fwd(const FwdState &dst, const FwdState &src, const te_ctx *c, h
   return hipMemcpyAsync(dst.x, src.x, sizeof(double) * fwd_doubles(c), hipMemcpyDeviceToDevice, st);
 }
 
-void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms, int block_threads) {
+void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms, int block_threads, int ppl) {
   s->iters = c.k;
   s->flags = c.flags;
   s->stop_iter = c.stop_iter;
   s->engine = engine;
   s->block_threads = engine == TE_ENGINE_BLOCK ? block_threads : 0;
+  s->paths_per_lane = engine == TE_ENGINE_BLOCK ? ppl : 0;
   s->final_alpha = c.alpha;
   s->beta = c.beta;
   s->r = c.r;
@@ -628,7 +636,8 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   if (engine == TE_ENGINE_BLOCK) {
     Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev};
     HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
-                              c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads, stream));
+                              c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads,
+                              o.paths_per_lane ? o.paths_per_lane : 1, stream));
   } else {
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
@@ -735,7 +744,8 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads);
+    fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads,
+               o.paths_per_lane ? o.paths_per_lane : 1);
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
@@ -1001,42 +1011,52 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
   DeviceScope dscope(b->device);
   HIPCHK(dscope.err);
   Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
-  int threads = o.block_threads;
-  if (threads == 0) {
-    if (b->tuned_threads == 0) {
-      // workgroup-size tuning on the first solve: 16 iterations of the batch with each candidate,
-      // timed with events; the fastest is kept (the outputs are overwritten by the solve below)
+  int threads = o.block_threads, ppl = o.paths_per_lane;
+  if (threads == 0 || ppl == 0) {
+    const std::pair<int, int> key(threads, ppl);
+    auto it = b->tuned.find(key);
+    if (it == b->tuned.end()) {
+      // tuning on the first such solve: 16 iterations of the batch with each candidate pair (the
+      // unspecified members vary), timed with events; the fastest is kept by the handle (the outputs
+      // are overwritten by the solve below)
       te_options t;
       te_default_options(&t);
       t.fixed_iters = 16;
       t.project = 0;
-      const int cand[3] = {1024, 512, 256};
+      const int cand_t[3] = {1024, 512, 256}, cand_p[4] = {1, 2, 4, 8};
       float best = 0.f;
+      std::pair<int, int> pick(0, 0);
       for (int i = 0; i < 3; ++i) {
-        s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
-        if (s != TE_OK) return s;
-        for (int rep = 0; rep < 2; ++rep) {  // the first launch also sets up the kernel
-          HIPCHK(hipEventRecord(b->ev0, stream));
-          HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev, b->d_out,
-                                    b->lds_bytes, cand[i], stream));
-          HIPCHK(hipEventRecord(b->ev1, stream));
-        }
-        HIPCHK(hipEventSynchronize(b->ev1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-        if (b->tuned_threads == 0 || ms < best) {
-          best = ms;
-          b->tuned_threads = cand[i];
+        if (threads != 0 && cand_t[i] != threads) continue;
+        for (int k = 0; k < 4; ++k) {
+          if (ppl != 0 && cand_p[k] != ppl) continue;
+          s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
+          if (s != TE_OK) return s;
+          for (int rep = 0; rep < 2; ++rep) {  // the first launch also sets up the kernel
+            HIPCHK(hipEventRecord(b->ev0, stream));
+            HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev, b->d_out,
+                                      b->lds_bytes, cand_t[i], cand_p[k], stream));
+            HIPCHK(hipEventRecord(b->ev1, stream));
+          }
+          HIPCHK(hipEventSynchronize(b->ev1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+          if (pick.first == 0 || ms < best) {
+            best = ms;
+            pick = std::make_pair(cand_t[i], cand_p[k]);
+          }
         }
       }
+      it = b->tuned.emplace(key, pick).first;
     }
-    threads = b->tuned_threads;
+    threads = it->second.first;
+    ppl = it->second.second;
   }
   s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   HIPCHK(hipEventRecord(b->ev0, stream));
   HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, o.project, x_out_dev, S_out_dev, b->d_out,
-                            b->lds_bytes, threads, stream));
+                            b->lds_bytes, threads, ppl, stream));
   HIPCHK(hipEventRecord(b->ev1, stream));
   if (stats) {
     HIPCHK(hipStreamSynchronize(stream));
@@ -1055,7 +1075,7 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
       fin.s = outs[k].s;
       fin.cap_viol = outs[k].cap_viol;
       fin.dem_viol = outs[k].dem_viol;
-      fill_stats(&stats[k], fin, TE_ENGINE_BLOCK, ms, threads);
+      fill_stats(&stats[k], fin, TE_ENGINE_BLOCK, ms, threads, ppl);
     }
   }
   return TE_OK;

@@ -240,22 +240,24 @@ def test_adaptive_solve_reaches_maxmin_waxman20(te, c1):
     assert opt >= 0.99
 
 
-@pytest.mark.parametrize("threads", [256, 512, 1024])
-def test_batch_equals_individual(te, threads):
+@pytest.mark.parametrize("threads,ppl", [(256, 1), (512, 1), (1024, 1), (256, 8), (512, 2), (1024, 4)])
+def test_batch_equals_individual(te, threads, ppl):
     """One launch over uneven instances gives each the same rates as its own workgroup-engine solve
-    with the same workgroup size (bit for bit)."""
+    with the same workgroup size and paths per lane (bit for bit)."""
     scen = W.failure_scenarios(0, n_scen=24)
     probs = [te.Problem(s) for s in scen]
     batch = te.Batch(probs)
-    opts = te.Options(fixed_iters=200, block_threads=threads)
+    opts = te.Options(fixed_iters=200, block_threads=threads, paths_per_lane=ppl)
     xb, Sb, stb = batch.solve(opts)
     xb = xb.cpu().numpy()
     off = 0
     for p, s, stt in zip(probs, scen, stb):
-        x, S, st = p.solve(te.Options(fixed_iters=200, engine=te.ENGINE_BLOCK, block_threads=threads))
+        x, S, st = p.solve(te.Options(fixed_iters=200, engine=te.ENGINE_BLOCK, block_threads=threads,
+                                      paths_per_lane=ppl))
         np.testing.assert_array_equal(xb[off:off + s.n_paths], x.cpu().numpy())
         assert stt["iters"] == st["iters"] == 200
         assert stt["block_threads"] == st["block_threads"] == threads
+        assert stt["paths_per_lane"] == st["paths_per_lane"] == ppl
         off += s.n_paths
 
 
@@ -275,18 +277,40 @@ def test_parity_block_workgroup_sizes(te, c1, threads):
 
 
 def test_batch_tuned_workgroup_size(te):
-    """block_threads = 0 on a batch: the size measured fastest on the first solve is kept, and the
-    result equals the forced solve at that size."""
+    """block_threads = paths_per_lane = 0 on a batch: the pair measured fastest on the first solve is
+    kept, and the result equals the forced solve with that pair; fixing one member tunes the other."""
     scen = W.failure_scenarios(1, n_scen=64)
     batch = te.Batch([te.Problem(s) for s in scen])
     x1, _, st1 = batch.solve(te.Options(fixed_iters=64))
-    t = st1[0]["block_threads"]
-    assert t in (256, 512, 1024) and all(s["block_threads"] == t for s in st1)
+    t, q = st1[0]["block_threads"], st1[0]["paths_per_lane"]
+    assert t in (256, 512, 1024) and q in (1, 2, 4, 8)
+    assert all(s["block_threads"] == t and s["paths_per_lane"] == q for s in st1)
     x2, _, st2 = batch.solve(te.Options(fixed_iters=64))
-    assert st2[0]["block_threads"] == t
-    x3, _, _ = batch.solve(te.Options(fixed_iters=64, block_threads=t))
+    assert (st2[0]["block_threads"], st2[0]["paths_per_lane"]) == (t, q)
+    x3, _, _ = batch.solve(te.Options(fixed_iters=64, block_threads=t, paths_per_lane=q))
     np.testing.assert_array_equal(x1.cpu().numpy(), x3.cpu().numpy())
-    print(f"tuned workgroup size for 64 scenarios: {t}")
+    _, _, st4 = batch.solve(te.Options(fixed_iters=64, paths_per_lane=1))
+    assert st4[0]["paths_per_lane"] == 1 and st4[0]["block_threads"] in (256, 512, 1024)
+    _, _, st5 = batch.solve(te.Options(fixed_iters=64, block_threads=256))
+    assert st5[0]["block_threads"] == 256 and st5[0]["paths_per_lane"] in (1, 2, 4, 8)
+    print(f"tuned for 64 scenarios: {t} threads, {q} paths per lane")
+
+
+@pytest.mark.parametrize("ppl", [2, 4, 8])
+@pytest.mark.parametrize("name", ["waxman20", "ragged0"])
+def test_parity_block_paths_per_lane(te, c1, ppl, name):
+    """The workgroup engine with 2, 4 and 8 paths per lane against the oracle (schedule replayed),
+    on the 20-node instance (8 path slots per demand) and the edge-case instance (1 to 64 paths)."""
+    inst = c1 if name == "waxman20" else W.ragged(0)
+    K = 256
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    opts = te.Options(fixed_iters=K, project=False, engine=te.ENGINE_BLOCK, block_threads=256, paths_per_lane=ppl,
+                      sched_beta=sb, sched_alpha=sa)
+    x, S, st = prob.solve(opts)
+    assert st["paths_per_lane"] == ppl
+    err = _report(f"{name} block ppl={ppl}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale, inst.demand)
+    assert err.max() <= REL
 
 
 def test_update_and_warm_start(te, c1, torch):
@@ -308,9 +332,10 @@ def test_update_and_warm_start(te, c1, torch):
 
 def test_invalid_options_rejected(te, c1):
     prob = te.Problem(c1)
-    with pytest.raises(te.TEError) as ex:
-        prob.solve(te.Options(beta0=-1.0))
-    assert ex.value.status == te.TE_ERR_INVALID
+    for bad in (dict(beta0=-1.0), dict(block_threads=128), dict(paths_per_lane=3)):
+        with pytest.raises(te.TEError) as ex:
+            prob.solve(te.Options(**bad))
+        assert ex.value.status == te.TE_ERR_INVALID
 
 
 def _golden(name):
