@@ -94,13 +94,13 @@ typedef struct {
   int32_t record;      /* 1: keep the (beta, alpha) schedule and checkpoints for te_grad */
   int32_t ckpt_every;  /* te_grad checkpoint spacing in iterations; default 16 */
   int32_t block_threads; /* workgroup engine: threads per workgroup, 256, 512 or 1024; 0 (default):
-                            1024 for single solves, and for batches the fastest of the three measured
-                            on the batch's first solve (kept by the batch handle) */
+                            1024 for single solves, tuned for batches (see paths_per_lane) */
   int32_t paths_per_lane; /* workgroup engine: paths of a demand held by one lane in the demand step,
                             1, 2, 4 or 8 (a demand with G path slots gets max(1, G / paths_per_lane)
-                            lanes); 0 (default): 1 for single solves, and for batches the fastest
-                            pair (block_threads, paths_per_lane) measured on the batch's first solve
-                            when both are 0 */
+                            lanes); 0 (default): 4 for single solves; for batches, the members
+                            of (block_threads, paths_per_lane) left at 0 are tuned on the batch's
+                            first such solve (every candidate timed over min(max(fixed_iters, 256),
+                            512) iterations) and kept by the handle */
   int32_t warm;        /* 1: continue from the state the handle's last graph-engine solve left (rates,
                           every dual, beta and alpha; alpha capped at alpha_target) instead of
                           initialising, e.g. after te_update; the iteration count restarts at 0.

@@ -98,6 +98,7 @@ constexpr int kThreads = 256;        // threads per workgroup of the graph-engin
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kLinkWaves = kLinkThreads / 64;
 constexpr int kBlockThreads = 1024;  // threads of the workgroup engine for single solves
+constexpr int kBlockPathsPerLane = 4;  // paths per lane of the workgroup engine for single solves
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
 struct BatchDesc {

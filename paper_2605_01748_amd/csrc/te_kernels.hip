@@ -737,27 +737,12 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
   const int lane = tid & (Gp - 1);
   const int groups = nth >> logGp;
   const int w = tid >> 6, l64 = tid & 63, nw = nth >> 6;
-  // this wavefront's part of the CSC entries for the link step, and the rank (among non-empty
-  // links) of the link holding its first entry
-  int4 bwt;
-  {
-    const int per = (nnz + nw - 1) / nw;
-    const int ja = min(nnz, w * per), jb = min(nnz, (w + 1) * per);
-    int lo = 0, hi = E - 1;  // last link e with lptr[e] <= ja: the non-empty link holding entry ja
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if ((int)lptr[mid] <= ja) lo = mid; else hi = mid - 1;
-    }
-    int a = 0, b = d.nzl;  // its rank: first position in nzl not below lo
-    while (a < b) {
-      const int mid = (a + b) >> 1;
-      if ((int)nzl[mid] < lo) a = mid + 1; else b = mid;
-    }
-    bwt = make_int4(ja, jb, a, 0);
-  }
+  // link step: Lg lanes per non-empty link (a power of two, about NT / #links, at most 64)
+  int logLg = 0;
+  while (logLg < 6 && (d.nzl << (logLg + 1)) <= nth) ++logLg;
+  const int Lg = 1 << logLg, lg = tid & (Lg - 1), links_per_pass = nth >> logLg;
   while (!cs.stop) {
     const double inv_f = cs.inv_f;
-    for (int k = tid; k < d.nzl; k += nth) Lx[k] = 0.0;  // link-load accumulators, by rank
     Dem dm;
     dm.alpha = cs.alpha;
     dm.binv = 1.0 / cs.beta;
@@ -824,20 +809,29 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
       }
     }
     __syncthreads();
-    // link step: loads by segmented sums over the CSC rows (each wavefront a contiguous part),
-    // then one thread per non-empty link
-    seg_rows_sum(lpf, x, 0, bwt, Lx);
-    __syncthreads();
-    for (int k = tid; k < d.nzl; k += nth) {
-      const int e = nzl[k];
-      const double load = Lx[k];
-      const int ne = lptr[e + 1] - lptr[e];
-      const double2 v = gq[e];
-      const double gold = v.x * inv_f;
-      const double gn = fmax(gold + (load - Cn[e]) / (double)(1 + ne), 0.0);
-      gq[e] = make_double2(gn, gold - gn);
-      dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
-      cap_v = fmax(cap_v, (load - Cn[e]) / Cn[e]);
+    // link step: each group of Lg lanes sums the new rates over one link's CSC entries (lane i
+    // takes entries i, i + Lg, ...; the group's sum by DPP butterflies, so the order is fixed), then
+    // the group's first lane updates the link's duals
+    for (int k0 = 0; k0 < d.nzl; k0 += links_per_pass) {
+      const int k = k0 + (tid >> logLg);
+      double load = 0.0;
+      int e = 0, ne = 0;
+      if (k < d.nzl) {
+        e = nzl[k];
+        const int j0 = lptr[e], j1 = lptr[e + 1];
+        ne = j1 - j0;
+#pragma unroll 4
+        for (int j = j0 + lg; j < j1; j += Lg) load += x[csc_path(lpf[j])];
+      }
+      load = group_sum_d(load, Lg);
+      if (k < d.nzl && lg == 0) {
+        const double2 v = gq[e];
+        const double gold = v.x * inv_f;
+        const double gn = fmax(gold + (load - Cn[e]) / (double)(1 + ne), 0.0);
+        gq[e] = make_double2(gn, gold - gn);
+        dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
+        cap_v = fmax(cap_v, (load - Cn[e]) / Cn[e]);
+      }
     }
     // partial sums and decision
     ds2 = wave_sum_d(ds2);

@@ -637,7 +637,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev};
     HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
                               c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads,
-                              o.paths_per_lane ? o.paths_per_lane : 1, stream));
+                              o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane, stream));
   } else {
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
@@ -745,7 +745,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads,
-               o.paths_per_lane ? o.paths_per_lane : 1);
+               o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane);
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
@@ -1016,13 +1016,11 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
     const std::pair<int, int> key(threads, ppl);
     auto it = b->tuned.find(key);
     if (it == b->tuned.end()) {
-      // tuning on the first such solve: 16 iterations of the batch with each candidate pair (the
-      // unspecified members vary), timed with events; the fastest is kept by the handle (the outputs
-      // are overwritten by the solve below)
-      te_options t;
-      te_default_options(&t);
-      t.fixed_iters = 16;
-      t.project = 0;
+      // tuning on the first such solve: each candidate pair (the unspecified members vary) runs the
+      // batch for min(max(fixed_iters, 256), 512) iterations after a short warm-up launch, timed
+      // with events; the fastest is kept by the handle for later solves too (the outputs are
+      // overwritten by the solve below)
+      const int K_t = std::min(std::max(o.fixed_iters, 256), 512);
       const int cand_t[3] = {1024, 512, 256}, cand_p[4] = {1, 2, 4, 8};
       float best = 0.f;
       std::pair<int, int> pick(0, 0);
@@ -1030,9 +1028,13 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
         if (threads != 0 && cand_t[i] != threads) continue;
         for (int k = 0; k < 4; ++k) {
           if (ppl != 0 && cand_p[k] != ppl) continue;
-          s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
-          if (s != TE_OK) return s;
-          for (int rep = 0; rep < 2; ++rep) {  // the first launch also sets up the kernel
+          for (int q = 0; q < 2; ++q) {  // q = 0: warm-up launch that also sets up the kernel
+            te_options t;
+            te_default_options(&t);
+            t.fixed_iters = q == 0 ? 8 : K_t;
+            t.project = 0;
+            s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
+            if (s != TE_OK) return s;
             HIPCHK(hipEventRecord(b->ev0, stream));
             HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev, b->d_out,
                                       b->lds_bytes, cand_t[i], cand_p[k], stream));
