@@ -87,17 +87,19 @@ def measured_traffic(kernel):
     return None if k is None else int(k["traffic_bytes"])
 
 
-def kernel_bytes(inst):
-    """Algorithmic bytes per launch of the two per-iteration kernels (int32 indices, FP64 path state
-    with an FP32 copy of the rates for the link kernel, FP64 per-link / per-demand values).  Each
-    kernel is charged what it must read or write once:
-      demand kernel: path row pointers 4 (P+1), link ids 4 nnz, x and u_neg read+write 32 P, FP32
-                     copy of x written 4 P, per-link (g, q) pairs 16 E, per demand pointer 4 +
-                     D 8 + u_dem and S read+write 32 -> 44 D
+def kernel_bytes(inst, hop_slots):
+    """Algorithmic bytes per launch of the two per-iteration kernels (FP64 path state with an FP32
+    copy of the rates for the link kernel, FP64 per-link / per-demand values).  Each kernel is
+    charged what it must read or write once:
+      demand kernel: the paths' link ids -- fixed-width 16-bit hop records 2 H P when the library
+                     uses them (H = hop_slots > 0), else row pointers 4 (P+1) and int32 ids 4 nnz --,
+                     x and u_neg read+write 32 P, FP32 copy of x written 4 P, per-link (g, q) pairs
+                     16 E, per demand pointer 4 + D 8 + u_dem and S read+write 32 -> 44 D
       link kernel:   CSC path ids 4 nnz, FP32 x read 4 P, (g, q) read+write 32 E, capacity 8 E,
                      non-empty link tables 8 E."""
     P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
-    b_dem = 4 * (P + 1) + 4 * nnz + 36 * P + 16 * E + 44 * D
+    ids = 2 * hop_slots * P if hop_slots > 0 else 4 * (P + 1) + 4 * nnz
+    b_dem = ids + 36 * P + 16 * E + 44 * D
     b_link = 4 * nnz + 4 * P + 48 * E
     return b_dem, b_link
 
@@ -176,7 +178,7 @@ def large_run(args, torch, te, W, dev):
     log(f"{inst.summary()} (built in {time.time() - t0:.1f}s)")
     prob = te.Problem(inst)
     ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=32)
-    b_dem, b_link = kernel_bytes(inst)
+    b_dem, b_link = kernel_bytes(inst, prob.info()["hop_slots"])
     rl = {}
     for name, ms, b in (("k_demand", ms_dem, b_dem), ("k_link", ms_link, b_link)):
         gbs = b / (ms * 1e-3) / 1e9
@@ -300,7 +302,7 @@ def main():
 
     # ---- per-kernel device time (HIP events around each launch) and roofline ----
     ms_dem, ms_link = prob.kernel_times(te.Options(engine=te.ENGINE_GRAPH), iters=min(K_star, 1024))
-    b_dem, b_link = kernel_bytes(inst)
+    b_dem, b_link = kernel_bytes(inst, prob.info()["hop_slots"])
     dom = ("k_demand", ms_dem, b_dem) if ms_dem * 1 >= ms_link else ("k_link", ms_link, b_link)
     achieved = dom[2] / (dom[1] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",

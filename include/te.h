@@ -239,8 +239,9 @@ void te_destroy(te_ctx *ctx);
 void te_destroy_batch(te_batch *batch);
 
 /* Sizes of a handle: n_links, n_paths, n_demands, nnz, max paths per demand, engine AUTO would pick,
- * workgroups of the graph engine's demand kernel and of its link kernel. */
-te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [8] */);
+ * workgroups of the graph engine's demand kernel and of its link kernel, and the 16-bit slots per
+ * path of the demand kernel's hop records (0: it reads the CSR path layout instead). */
+te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [9] */);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *te_last_error(void);

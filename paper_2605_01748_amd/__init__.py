@@ -200,11 +200,11 @@ class Problem:
         self.n_links, self.n_paths, self.n_demands = cap.shape[0], pptr.shape[0] - 1, dem.shape[0]
 
     def info(self):
-        sz = np.zeros(8, np.int64)
+        sz = np.zeros(9, np.int64)
         _check(library().te_info(self._h, sz.ctypes.data))
         return dict(n_links=int(sz[0]), n_paths=int(sz[1]), n_demands=int(sz[2]), nnz=int(sz[3]),
                     max_paths=int(sz[4]), auto_engine=int(sz[5]), demand_workgroups=int(sz[6]),
-                    link_workgroups=int(sz[7]))
+                    link_workgroups=int(sz[7]), hop_slots=int(sz[8]))
 
     def update(self, capacity=None, demand=None):
         c = None if capacity is None else np.ascontiguousarray(capacity, np.float64)

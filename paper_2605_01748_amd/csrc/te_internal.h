@@ -58,7 +58,13 @@ struct Prob {
   // per wavefront of the link kernels ([nB * kLinkWaves]): its CSC entry range [x, y) and the rank
   // (index into nzlink) of the link holding entry x, precomputed so that no wavefront searches
   const int4 *wtab;
+  // per path, its link ids as H 16-bit slots in path order, unused slots 0xffff (H a multiple of 4,
+  // at most kMaxHopSlots); H = 0 when some path has more hops or a link id does not fit 16 bits
+  const uint16_t *hops;
+  int32_t H;
 };
+
+constexpr int kMaxHopSlots = 16;
 
 // Iteration state on the device.
 struct State {

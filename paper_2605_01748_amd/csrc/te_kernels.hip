@@ -202,7 +202,29 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
     np = p.dptr[c + 1] - r0;
     on = lane < np;
     r = r0 + (on ? lane : 0);
-    if (on) {
+    if (on && p.H > 0) {
+      // the path's fixed-width hop record (16-bit link ids in path order, 0xffff past the end):
+      // its loads depend on r only, then all (g, q) pairs are gathered together
+      xr = s.x[r];
+      ung = s.uneg[r];
+      const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
+      uint2 w[kMaxHopSlots / 4];
+#pragma unroll
+      for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+      n = 0;
+#pragma unroll
+      for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+        const unsigned id[4] = {w[q].x & 0xffffu, w[q].x >> 16, w[q].y & 0xffffu, w[q].y >> 16};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (id[u] != 0xffffu) {
+            const double2 v = s.gq[id[u]];
+            sg += v.x;
+            sq += v.y;
+            ++n;
+          }
+      }
+    } else if (on) {
       const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
       n = i1 - i0;
       xr = s.x[r];

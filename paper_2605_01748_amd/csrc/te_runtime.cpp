@@ -88,7 +88,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 struct te_ctx {
   int device = 0;
-  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0;
+  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0;
   double scale = 1.0;
   // host layout (kept for batches and updates)
   std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
@@ -108,6 +108,7 @@ struct te_ctx {
   int32_t sched_cap = 0;
   int32_t *d_i32 = nullptr;
   int4 *d_wtab = nullptr;
+  uint16_t *d_hops = nullptr;
   double *d_Dn = nullptr;
   double *d_Cn = nullptr;
   // workgroup engine (single instance)
@@ -555,6 +556,23 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     if (hipMemcpy(c->d_i32, pool.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice) != hipSuccess)
       return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the index pool failed"));
   }
+  // fixed-width hop records of the demand kernel (when every path fits kMaxHopSlots and every
+  // link id fits 16 bits): the row-pointer load before the link ids is then not needed
+  {
+    int maxh = 0;
+    for (int32_t r = 0; r < c->P; ++r) maxh = std::max(maxh, c->pptr[r + 1] - c->pptr[r]);
+    c->H = (maxh + 3) & ~3;
+    if (c->H <= kMaxHopSlots && c->E < 0xffff) {
+      std::vector<uint16_t> hops((size_t)c->P * c->H, (uint16_t)0xffff);
+      for (int32_t r = 0; r < c->P; ++r)
+        for (int32_t i = c->pptr[r]; i < c->pptr[r + 1]; ++i)
+          hops[(size_t)r * c->H + (i - c->pptr[r])] = (uint16_t)c->plinks[i];
+      if (dalloc(&c->d_hops, hops.size()) != hipSuccess)
+        return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
+      if (hipMemcpy(c->d_hops, hops.data(), sizeof(uint16_t) * hops.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the hop records failed"));
+    }
+  }
   te_status s = upload_values(c);
   if (s != TE_OK) return cleanup_fail(s);
   Prob &p = c->prob;
@@ -574,6 +592,8 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.nzptr = p.nzlink + c->nzlink.size();
   p.blk = p.nzptr + c->nzptr.size();
   p.wtab = c->d_wtab;
+  p.hops = c->d_hops;
+  p.H = c->d_hops ? c->H : 0;
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -603,6 +623,7 @@ te_status te_info(const te_ctx *c, int64_t *sz) {
   sz[5] = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   sz[6] = c->st.nA;
   sz[7] = c->st.nB;
+  sz[8] = c->d_hops ? c->H : 0;
   return TE_OK;
 }
 
@@ -904,7 +925,7 @@ void te_destroy(te_ctx *c) {
   free_fwd(c->work);
   void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.xf, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
-                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab};
+                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_params) (void)hipHostFree(c->h_params);
