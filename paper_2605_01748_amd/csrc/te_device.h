@@ -157,11 +157,13 @@ __device__ __forceinline__ double h_of(double S, const Dem &c) {
   return fmax(S - c.D + c.u, 0.0) - pow_neg_alpha(S, invS, c.alpha) * c.binv;
 }
 
-// F(S) and F'(S) summed over the group (uniform inside the group).
-__device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, int G, double &F, double &dF) {
+// F(S), F'(S) and the smooth part of F''(S), summed over the group (uniform inside the group).
+__device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, int G, double &F, double &dF,
+                                       double &d2F) {
   if (c.alpha > 0.0 && !(S > 0.0)) {
     F = INFINITY;
     dF = -INFINITY;
+    d2F = 0.0;
     return;
   }
   const double t = S - c.D + c.u;
@@ -177,13 +179,18 @@ __device__ __forceinline__ void F_eval(double S, const Lane &L, const Dem &c, in
   dv = group_sum_d(dv, G);
   F = v - S;
   dF = -dh * dv - 1.0;
+  // plain Newton steps here: in the device-wide kernel a wavefront holds eight demands, whose
+  // slowest root decides its time, and the curvature correction measured no faster there
+  d2F = 0.0;
 }
 
 template <int PPL>
-__device__ __forceinline__ void F_eval(double S, const LaneN<PPL> &L, const Dem &c, int G, double &F, double &dF) {
+__device__ __forceinline__ void F_eval(double S, const LaneN<PPL> &L, const Dem &c, int G, double &F, double &dF,
+                                       double &d2F) {
   if (c.alpha > 0.0 && !(S > 0.0)) {
     F = INFINITY;
     dF = -INFINITY;
+    d2F = 0.0;
     return;
   }
   const double t = S - c.D + c.u;
@@ -204,15 +211,21 @@ __device__ __forceinline__ void F_eval(double S, const LaneN<PPL> &L, const Dem 
   dv = group_sum_d(dv, G);
   F = v - S;
   dF = -dh * dv - 1.0;
+  // away from the kinks F'' = -h''(S) dv with h'' = -alpha (alpha + 1) S^(-alpha-2) / beta
+  d2F = c.alpha > 0.0 ? c.alpha * (c.alpha + 1.0) * pw * c.binv * invS * invS * dv : 0.0;
 }
 
 // Safeguarded Newton (appendix B.2) from the warm start S0: every evaluation narrows the bracket
 // [lo, hi] with F(lo) > 0 > F(hi) (ends infinite until a sign of each kind has been seen); the next
-// point is the Newton point when it lies strictly inside the bracket (and stays positive for
-// alpha > 0), else the midpoint once both ends are known, else an expansion (doubling steps, or
-// halving towards 0 for alpha > 0).  Stops when the Newton correction or the bracket falls below
-// 1e-13 max(1, |S|) (normalised units, where F's rounding noise is ~1e-16 of its O(1) terms).
-// Mean cost on the 150-node instance: 2.1 evaluations of F per demand and iteration.
+// point is the Newton point -- with Halley's correction for the curvature of the S^-alpha term,
+// step / (1 - step F'' / (2 F')), when F'' is given and that factor lies in (1/2, 2): cubic instead
+// of quadratic convergence on the smooth part, for the price of one product per evaluation; the
+// workgroup engine, whose wavefronts hold up to 64 demands, gives F'' -- when it lies
+// strictly inside the bracket (and stays positive for alpha > 0), else the midpoint once both ends
+// are known, else an expansion (doubling steps, or halving towards 0 for alpha > 0).  Stops when
+// the correction or the bracket falls below 1e-13 max(1, |S|) (normalised units, where F's
+// rounding noise is ~1e-16 of its O(1) terms).  The root is the same as the oracle's to that
+// tolerance; only the path to it is shorter.
 template <class LaneT>
 __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *evals) {
   const double tol = 1e-13;
@@ -220,8 +233,8 @@ __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *e
   double lo = -INFINITY, hi = INFINITY, expand = 0.0;
   *evals = 0;
   for (int it = 0; it < 1200; ++it) {
-    double F, dF;
-    F_eval(S, L, c, G, F, dF);
+    double F, dF, d2F;
+    F_eval(S, L, c, G, F, dF, d2F);
     ++*evals;
     if (F == 0.0) return S;
     if (F > 0.0) lo = S; else hi = S;
@@ -230,7 +243,12 @@ __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *e
     double Sn = 0.0;
     bool ok = isfinite(F) && isfinite(dF) && dF < 0.0;
     if (ok) {
-      const double step = F * rcp_refined(dF);
+      const double rdF = rcp_refined(dF);
+      double step = F * rdF;
+      if (d2F != 0.0) {
+        const double den = 1.0 - 0.5 * step * d2F * rdF;
+        if (den > 0.5 && den < 2.0) step *= rcp_refined(den);
+      }
       if (fabs(step) <= tol * scale) return S - step;  // correction below tolerance
       Sn = S - step;
       ok = Sn > lo && Sn < hi && !(c.alpha > 0.0 && !(Sn > 0.0));

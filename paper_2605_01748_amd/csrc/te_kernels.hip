@@ -4,14 +4,15 @@
 // Graph engine (large instances): one iteration = two device-wide kernels,
 //   k_demand: per demand (G lanes, one per path): gather of (g_e, q_e) along each path,
 //             sum equation by Newton-bisection, rate update, u_dem / u_neg updates;
-//   k_link:   per link (one wavefront): segmented sum of the new rates over the link's CSC
-//             list in FP64, capacity/consensus dual update.
+//   k_link:   per run of links (one workgroup; its wavefronts walk contiguous parts of the CSC
+//             list): segmented FP64 sums of the new rates, capacity/consensus dual update.
 // Both kernels first apply the control decision of the previous iteration (residual balancing,
 // alpha step, stop) redundantly in every workgroup from the previous iteration's partial sums,
 // so no extra launch or grid-wide barrier is needed; iterations are replayed from a HIP graph.
 //
 // Workgroup engine (small instances, batches): one workgroup runs the whole solve with the
-// instance resident in LDS and __syncthreads() between the steps.
+// instance resident in LDS and __syncthreads() between the steps; PPL paths per lane in the
+// demand step, a group of lanes per link in the link step.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
