@@ -62,9 +62,16 @@ struct Prob {
   // at most kMaxHopSlots); H = 0 when some path has more hops or a link id does not fit 16 bits
   const uint16_t *hops;
   int32_t H;
+  // demand kernel of the graph engine: paths per lane (1 = one lane per path) and log2 of its
+  // lanes per demand, max(1, G / ppl)
+  int32_t ppl, logGp;
 };
 
 constexpr int kMaxHopSlots = 16;
+// graph engine: instances with at least kMultiLanes lane slots (demands x G) run the demand step
+// with min(G, kMultiPaths) paths per lane
+constexpr int64_t kMultiLanes = 1 << 20;
+constexpr int kMultiPaths = 2;
 
 // Iteration state on the device.
 struct State {

@@ -180,6 +180,49 @@ __global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
 // ------------------------------------------------------------------------------------------
 // Step a1 + a2: gather along paths, per-demand Newton-bisection, rate and dual updates.
 // ------------------------------------------------------------------------------------------
+// Sums of g and q over path r's links, and its hop count.  With hop records (H > 0) the link ids
+// come from the path's fixed-width record (16-bit ids in path order, 0xffff past the end), whose
+// loads depend on r only; all (g, q) pairs are then gathered together.  Otherwise from the CSR
+// layout, eight link ids, then their pairs, at a time.
+__device__ __forceinline__ void gather_path(const Prob &p, const State &s, int r, double &sg, double &sq, int &n) {
+  sg = 0.0;
+  sq = 0.0;
+  if (p.H > 0) {
+    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
+    uint2 w[kMaxHopSlots / 4];
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+    n = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      const unsigned id[4] = {w[q].x & 0xffffu, w[q].x >> 16, w[q].y & 0xffffu, w[q].y >> 16};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (id[u] != 0xffffu) {
+          const double2 v = s.gq[id[u]];
+          sg += v.x;
+          sq += v.y;
+          ++n;
+        }
+    }
+  } else {
+    const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
+    n = i1 - i0;
+    for (int ib = i0; ib < i1; ib += 8) {
+      int e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e[u] >= 0) {
+          const double2 v = s.gq[e[u]];
+          sg += v.x;
+          sq += v.y;
+        }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
@@ -203,45 +246,10 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
     np = p.dptr[c + 1] - r0;
     on = lane < np;
     r = r0 + (on ? lane : 0);
-    if (on && p.H > 0) {
-      // the path's fixed-width hop record (16-bit link ids in path order, 0xffff past the end):
-      // its loads depend on r only, then all (g, q) pairs are gathered together
+    if (on) {
       xr = s.x[r];
       ung = s.uneg[r];
-      const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
-      uint2 w[kMaxHopSlots / 4];
-#pragma unroll
-      for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
-      n = 0;
-#pragma unroll
-      for (int q = 0; q < kMaxHopSlots / 4; ++q) {
-        const unsigned id[4] = {w[q].x & 0xffffu, w[q].x >> 16, w[q].y & 0xffffu, w[q].y >> 16};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (id[u] != 0xffffu) {
-            const double2 v = s.gq[id[u]];
-            sg += v.x;
-            sq += v.y;
-            ++n;
-          }
-      }
-    } else if (on) {
-      const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
-      n = i1 - i0;
-      xr = s.x[r];
-      ung = s.uneg[r];
-      for (int ib = i0; ib < i1; ib += 8) {  // link ids of up to 8 hops, then their (g, q) pairs
-        int e[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-          if (e[u] >= 0) {
-            const double2 v = s.gq[e[u]];
-            sg += v.x;
-            sq += v.y;
-          }
-      }
+      gather_path(p, s, r, sg, sq, n);
     }
   }
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
@@ -275,6 +283,101 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
       ds2 = (xn - xr) * (xn - xr);
       dr2 = (un - L.un) * (un - L.un);
     }
+    if (lane == 0) {
+      const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
+      s.udem[c] = ud;
+      s.S[c] = Sst;
+      dr2 += (ud - dm.u) * (ud - dm.u);
+      dem_v = (Ssum - dm.D) / dm.D;
+    }
+  }
+  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + bl) * 4);
+}
+
+// The same step with PPL (2, 4 or 8) paths per lane, for instances large enough to be bound by
+// issue and bandwidth rather than latency: a demand with G path slots gets Gp = max(1, G / PPL)
+// lanes (p.logGp), lane l holding the demand's paths l, l + Gp, ...; the per-demand part of the root
+// solve is then replicated over fewer lanes, and its Newton steps get Halley's correction.
+template <int PPL>
+__global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, const Params *prmp, int par) {
+  const Params &prm = *prmp;
+  __shared__ Ctrl cs;
+  CtrlPrefetch cp;
+  if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
+  const int logGp = p.logGp, Gp = 1 << logGp;
+  const int t = threadIdx.x;
+  const int lane = t & (Gp - 1);
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int c = bl * (kThreads >> logGp) + (t >> logGp);
+  int r0 = 0, np = 0;
+  double Dc = 0.0, udc = 0.0, S0 = 0.0;
+  double xr[PPL], ung[PPL], sg[PPL], sq[PPL];
+  int n[PPL];
+  unsigned on = 0u;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    xr[j] = ung[j] = sg[j] = sq[j] = 0.0;
+    n[j] = 1;
+  }
+  if (c < p.D) {
+    Dc = p.Dn[c];
+    udc = s.udem[c];
+    S0 = s.S[c];
+    r0 = p.dptr[c];
+    np = p.dptr[c + 1] - r0;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const int idx = lane + j * Gp;
+      if (idx < np) {
+        const int r = r0 + idx;
+        on |= 1u << j;
+        xr[j] = s.x[r];
+        ung[j] = s.uneg[r];
+        gather_path(p, s, r, sg[j], sq[j], n[j]);
+      }
+    }
+  }
+  if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
+  __syncthreads();
+  if (cs.stop) return;
+  const double inv_f = cs.inv_f;
+  double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
+  if (c < p.D) {
+    LaneN<PPL> L;
+    L.on = on;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      const bool oj = (on >> j) & 1u;
+      L.a[j] = oj ? (double)n[j] * xr[j] - (sg[j] * inv_f - sq[j]) : 0.0;
+      L.un[j] = ung[j] * inv_f;
+      L.n[j] = (double)n[j];
+      L.rn[j] = 1.0 / (double)n[j];
+      L.rn1[j] = 1.0 / (double)(n[j] + 1);
+    }
+    Dem dm;
+    dm.D = Dc;
+    dm.u = udc * inv_f;
+    dm.alpha = cs.alpha;
+    dm.binv = 1.0 / cs.beta;
+    int steps;
+    const double Sst = sum_root(S0, L, dm, Gp, &steps);
+    const double h = h_of(Sst, dm);
+    double xsum = 0.0;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      if (!((on >> j) & 1u)) continue;
+      const int r = r0 + lane + j * Gp;
+      const double b = L.a[j] - h;
+      const double xn = (b >= L.n[j] * L.un[j]) ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
+      const double un = fmax(L.un[j] - xn, 0.0);
+      s.x[r] = xn;
+      s.xf[r] = (float)xn;
+      s.uneg[r] = un;
+      xsum += xn;
+      ds2 += (xn - xr[j]) * (xn - xr[j]);
+      dr2 += (un - L.un[j]) * (un - L.un[j]);
+    }
+    const double Ssum = group_sum_d(xsum, Gp);
     if (lane == 0) {
       const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
       s.udem[c] = ud;
@@ -1122,9 +1225,10 @@ hipError_t launch_adj_seed(const Prob &p, const AdjState &a, const float *dS, hi
   return hipGetLastError();
 }
 
-hipError_t launch_adj_iteration(const Prob &p, int nA, int nB, const FwdState &fin, const FwdState &fout,
+hipError_t launch_adj_iteration(const Prob &p, int nB, const FwdState &fin, const FwdState &fout,
                                 const AdjState &a, double beta, double alpha, double rho, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_demand, dim3(nA), dim3(kThreads), 0, st, p, fin, fout, a, beta, alpha, rho);
+  const int nAdj = (p.D + (kThreads >> p.logG) - 1) / (kThreads >> p.logG);  // G lanes per demand
+  hipLaunchKernelGGL(k_adj_demand, dim3(nAdj), dim3(kThreads), 0, st, p, fin, fout, a, beta, alpha, rho);
   hipLaunchKernelGGL(k_adj_link, dim3(nB), dim3(kLinkThreads), 0, st, p, fout, a, rho);
   return hipGetLastError();
 }
@@ -1158,17 +1262,37 @@ hipError_t launch_warm(const Prob &p, const State &s, const Params *prm, double 
   return hipGetLastError();
 }
 
+// the demand kernel for the handle's paths per lane (p.ppl); with ev0/ev1 the events are attached
+// to the dispatch itself (start and end of the kernel's execution), so their difference excludes
+// the queueing of separate event packets
+template <class K>
+static void launch_demand_k(K kern, const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, dim3(s.nA), dim3(kThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
+  else
+    hipLaunchKernelGGL(kern, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
+}
+
+static void launch_demand_kernel(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                                 hipEvent_t ev0, hipEvent_t ev1) {
+  switch (p.ppl) {
+    case 2: launch_demand_k(k_demand_multi<2>, p, s, prm, par, st, ev0, ev1); break;
+    case 4: launch_demand_k(k_demand_multi<4>, p, s, prm, par, st, ev0, ev1); break;
+    case 8: launch_demand_k(k_demand_multi<8>, p, s, prm, par, st, ev0, ev1); break;
+    default: launch_demand_k(k_demand, p, s, prm, par, st, ev0, ev1);
+  }
+}
+
 hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
-  hipLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, p, s, prm, par);
+  launch_demand_kernel(p, s, prm, par, st, nullptr, nullptr);
   hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
   return hipGetLastError();
 }
 
-// Timed launches: the events are attached to the dispatch itself (start and end of the kernel's
-// execution), so their difference excludes the queueing of separate event packets.
 hipError_t launch_demand_timed(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
                                hipEvent_t ev0, hipEvent_t ev1) {
-  hipExtLaunchKernelGGL(k_demand, dim3(s.nA), dim3(kThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
+  launch_demand_kernel(p, s, prm, par, st, ev0, ev1);
   return hipGetLastError();
 }
 

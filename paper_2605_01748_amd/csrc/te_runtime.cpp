@@ -33,7 +33,7 @@ hipError_t launch_block_solve(const BatchDesc *, int, const Pools &, const Param
                               BatchOut *, size_t, int, int, hipStream_t);
 size_t block_lds_bytes(int E, int P, int D, int nnz);
 hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStream_t);
-hipError_t launch_adj_iteration(const Prob &, int, int, const FwdState &, const FwdState &, const AdjState &, double,
+hipError_t launch_adj_iteration(const Prob &, int, const FwdState &, const FwdState &, const AdjState &, double,
                                 double, double, hipStream_t);
 hipError_t launch_adj_x0(const Prob &, const AdjState &, hipStream_t);
 }  // namespace te
@@ -88,7 +88,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 struct te_ctx {
   int device = 0;
-  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0;
+  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0, ppl = 1, logGp = 0;
   double scale = 1.0;
   // host layout (kept for batches and updates)
   std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
@@ -342,6 +342,37 @@ te_status capture_chunk(te_ctx *c, const State &st, hipGraphExec_t *out) {
 
 te_status build_chunk_graph(te_ctx *c, hipStream_t) { return capture_chunk(c, c->st, &c->chunk); }
 
+// Paths per lane of the graph engine's demand kernel: one lane per path, or -- for instances with
+// at least kMultiLanes lane slots (demands x G), where that kernel is bound by issue and bandwidth
+// rather than latency -- min(G, kMultiPaths).
+int default_graph_ppl(const te_ctx *c) {
+  return (int64_t)c->D * c->G >= kMultiLanes ? std::min(c->G, kMultiPaths) : 1;
+}
+
+void set_graph_ppl(te_ctx *c, int ppl) {
+  int logp = 0;
+  while ((1 << logp) < ppl) ++logp;
+  c->ppl = ppl;
+  c->logGp = c->logG > logp ? c->logG - logp : 0;
+  c->st.nA = (c->D + (kThreads >> c->logGp) - 1) / (kThreads >> c->logGp);
+  c->prob.ppl = c->ppl;
+  c->prob.logGp = c->logGp;
+}
+
+// The option's paths per lane (0: the default) for the graph engine; a change recaptures the
+// iteration graphs, which hold the demand kernel's launch shape.
+te_status select_graph_ppl(te_ctx *c, const te_options &o) {
+  const int want = o.paths_per_lane ? o.paths_per_lane : default_graph_ppl(c);
+  if (want == c->ppl) return TE_OK;
+  HIPCHK(hipDeviceSynchronize());  // no launch of the old graphs may still be in flight
+  if (c->chunk) HIPCHK(hipGraphExecDestroy(c->chunk));
+  if (c->rec_chunk) HIPCHK(hipGraphExecDestroy(c->rec_chunk));
+  c->chunk = nullptr;
+  c->rec_chunk = nullptr;
+  set_graph_ppl(c, want);
+  return TE_OK;
+}
+
 // An iteration state (x, u_neg, u_dem, S, (g, q)) lives in one block, x | u_neg | u_dem | S | gq,
 // so that a checkpoint or a segment step is one copy.
 size_t fwd_doubles(const te_ctx *c) { return 2 * (size_t)c->P + 2 * (size_t)c->D + 2 * (size_t)c->E; }
@@ -393,7 +424,7 @@ void fill_stats(te_stats *s, const Ctrl &c, int engine, double ms, int block_thr
   s->stop_iter = c.stop_iter;
   s->engine = engine;
   s->block_threads = engine == TE_ENGINE_BLOCK ? block_threads : 0;
-  s->paths_per_lane = engine == TE_ENGINE_BLOCK ? ppl : 0;
+  s->paths_per_lane = ppl;
   s->final_alpha = c.alpha;
   s->beta = c.beta;
   s->r = c.r;
@@ -513,11 +544,13 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   // index pool: pptr | plinks | dptr | lptr | lpaths
   const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz + c->nnz + c->nzlink.size() +
                     c->nzptr.size() + c->blk.size();
-  const int nA = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
+  // demand kernel mapping (partials are allocated for one lane per path, the largest grid)
+  set_graph_ppl(c, default_graph_ppl(c));
+  const int nA1 = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
             dalloc(&c->d_Cn, c->E) == hipSuccess && alloc_fwd(c->work, c) == hipSuccess &&
             dalloc(&c->st.xf, c->P) == hipSuccess &&
-            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA * 4) == hipSuccess &&
+            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA1 * 4) == hipSuccess &&
             dalloc(&c->st.partB, (size_t)2 * nB * 4) == hipSuccess &&
             dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
             dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
@@ -539,7 +572,6 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
       hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->pe[0]) != hipSuccess ||
       hipEventCreate(&c->pe[1]) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "event creation failed"));
-  c->st.nA = nA;
   c->st.nB = nB;
   {
     std::vector<int32_t> pool;
@@ -594,6 +626,8 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.wtab = c->d_wtab;
   p.hops = c->d_hops;
   p.H = c->d_hops ? c->H : 0;
+  p.ppl = c->ppl;
+  p.logGp = c->logGp;
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -660,6 +694,8 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
                               c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads,
                               o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane, stream));
   } else {
+    s = select_graph_ppl(c, o);
+    if (s != TE_OK) return s;
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
     if (o.warm)
@@ -766,7 +802,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads,
-               o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane);
+               engine == TE_ENGINE_BLOCK ? (o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane) : c->ppl);
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
@@ -784,6 +820,8 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
   hipStream_t stream = (hipStream_t)hip_stream;
   DeviceScope dscope(c->device);
   HIPCHK(dscope.err);
+  s = select_graph_ppl(c, o);
+  if (s != TE_OK) return s;
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   std::vector<hipEvent_t> ev(4 * (size_t)iters, nullptr);
@@ -900,7 +938,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
     }
     for (int k = k1 - 1; k >= k0; --k) {
       const double rho = k > 0 ? lb[k - 1] / lb[k] : 1.0;
-      HIPCHK(launch_adj_iteration(c->prob, c->st.nA, c->st.nB, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
+      HIPCHK(launch_adj_iteration(c->prob, c->st.nB, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
                                   la[k], rho, stream));
     }
   }

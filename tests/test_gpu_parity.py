@@ -115,6 +115,7 @@ def test_parity_hierarchical_full_size(te):
     assert prob.info()["link_workgroups"] <= 512
     x, S, st = _gpu_raw(te, prob, K, sb, sa, te.ENGINE_GRAPH)
     assert st["iters"] == K
+    assert st["paths_per_lane"] == 2  # the default for instances of this size
     err = _report(f"hierarchical 1000-node graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, inst.demand)
     assert err.max() <= REL
 
@@ -328,6 +329,25 @@ def test_update_and_warm_start(te, c1, torch):
     np.testing.assert_array_equal(xa.cpu().numpy(), xb.cpu().numpy())
     xw, Sw, stw = prob.solve(te.Options(fixed_iters=50), x0=x)
     assert np.all(np.isfinite(xw.cpu().numpy()))
+
+
+@pytest.mark.parametrize("ppl", [2, 4, 8])
+@pytest.mark.parametrize("name", ["waxman20", "ragged0", "waxman150"])
+def test_parity_graph_paths_per_lane(te, c1, c2, ppl, name):
+    """The graph engine's demand kernel with 2, 4 and 8 paths per lane (lane groups of
+    max(1, G / ppl) lanes per demand) against the oracle, schedule replayed; the handle switches
+    back to one path per lane afterwards and still matches."""
+    inst = {"waxman20": c1, "waxman150": c2}.get(name) or W.ragged(0)
+    K = 64 if name == "waxman150" else 256
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    for q in (ppl, 1):
+        opts = te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, paths_per_lane=q,
+                          sched_beta=sb, sched_alpha=sa)
+        x, S, st = prob.solve(opts)
+        assert st["paths_per_lane"] == q
+        err = _report(f"{name} graph ppl={q}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale, inst.demand)
+        assert err.max() <= REL
 
 
 def test_invalid_options_rejected(te, c1):
