@@ -218,8 +218,8 @@ def main():
     ap.add_argument("--cache-dir", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              f"sharding is a design note, not an implemented path", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU (got --gpus {args.gpus}); sharding across GPUs is "
+              f"described in the design notes, not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
