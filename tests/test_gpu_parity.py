@@ -118,6 +118,19 @@ def test_parity_hierarchical_full_size(te):
     assert st["paths_per_lane"] == 2  # the default for instances of this size
     err = _report(f"hierarchical 1000-node graph K={K} ({st['ms']:.3f} ms)", S, r.S_raw * r.scale, inst.demand)
     assert err.max() <= REL
+    # Algorithm 2 at full size (links carrying up to ~10^5 paths go through the radix selection):
+    # feasible, and the same per-demand sums as the oracle's Algorithm 2 on the GPU's own rates
+    xp, Sp, stp = prob.solve(te.Options(fixed_iters=K, project=True, engine=te.ENGINE_GRAPH,
+                                        sched_beta=sb, sched_alpha=sa))
+    xp = xp.cpu().numpy().astype(np.float64)
+    assert np.all(xp >= 0)
+    assert np.all(O.link_loads(inst, xp) <= inst.capacity * (1 + 1e-7))
+    assert np.all(O.demand_sums(inst, xp) <= inst.demand * (1 + 1e-7))
+    ref = O.project(inst, x.astype(np.float64), stp["final_alpha"])
+    d = np.abs(O.demand_sums(inst, xp) - O.demand_sums(inst, ref))
+    print(f"hierarchical 1000-node projection: max |dS| {d.max():.3e} (max D {inst.demand.max():.3e})")
+    np.testing.assert_allclose(O.demand_sums(inst, xp), O.demand_sums(inst, ref), rtol=1e-5,
+                               atol=1e-6 * inst.capacity.max())
 
 
 @pytest.mark.parametrize("K", [16, 128])
@@ -329,6 +342,44 @@ def test_update_and_warm_start(te, c1, torch):
     np.testing.assert_array_equal(xa.cpu().numpy(), xb.cpu().numpy())
     xw, Sw, stw = prob.solve(te.Options(fixed_iters=50), x0=x)
     assert np.all(np.isfinite(xw.cpu().numpy()))
+
+
+def test_workgroup_engine_at_its_lds_limit(te):
+    """The largest edge-case instance (1 to 64 paths per demand, 1 to 12 hops) that the automatic
+    choice still runs inside one workgroup, i.e. within ~156 KB of LDS: parity with the oracle for
+    several workgroup shapes, alone and in a batch with a small instance; one demand more and the
+    workgroup engine refuses it (the automatic choice moves to the graph engine)."""
+    big, over = None, None
+    for nd in range(60, 400, 8):
+        inst = W.ragged(3, n_links=300, n_demands=nd)
+        if te.Problem(inst).info()["auto_engine"] == te.ENGINE_BLOCK:
+            big = inst
+        else:
+            over = inst
+            break
+    assert big is not None and over is not None
+    print(f"largest workgroup-engine instance: {big.summary()}")
+    K = 64
+    r, sb, sa = _oracle_run(big, K)
+    want = r.S_raw * r.scale
+    prob = te.Problem(big)
+    for threads, ppl in ((256, 1), (256, 8), (512, 2), (1024, 4)):
+        x, S, st = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_BLOCK, block_threads=threads,
+                                         paths_per_lane=ppl, sched_beta=sb, sched_alpha=sa))
+        err = _report(f"LDS-limit instance threads={threads} ppl={ppl}", S.cpu().numpy().astype(np.float64), want,
+                      big.demand)
+        assert err.max() <= REL
+    small = W.ragged(0)
+    batch = te.Batch([te.Problem(big), te.Problem(small), te.Problem(big)])
+    xb, Sb, stb = batch.solve(te.Options(fixed_iters=K, project=False, block_threads=256, paths_per_lane=8,
+                                         sched_beta=sb, sched_alpha=sa))
+    Sb = Sb.cpu().numpy().astype(np.float64)
+    for off in (0, big.n_demands + small.n_demands):
+        assert _rel_err(Sb[off:off + big.n_demands], want, big.demand).max() <= REL
+    with pytest.raises(te.TEError):
+        te.Problem(over).solve(te.Options(fixed_iters=4, engine=te.ENGINE_BLOCK))
+    _, S_over, st_over = te.Problem(over).solve(te.Options(fixed_iters=4))
+    assert st_over["engine"] == te.ENGINE_GRAPH
 
 
 @pytest.mark.parametrize("ppl", [2, 4, 8])
