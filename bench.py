@@ -12,11 +12,19 @@ latency-shortest paths per pair.  K* is the smallest iteration budget on a geome
 projected allocation reaches optimality >= 0.99 against the exact max-min allocation (progressive
 filling LPs, stored in tests/golden).
 
+Besides the metric the JSON line carries the roofline of the dominant kernel, the FP64 oracle on
+the host (cpu_baseline), the drift-adjusted optimality and a warm start under synthetic drift
+(dao), the batch (batched), the gradient (grad) and the 1,000-node instance's per-iteration kernels
+in the bandwidth regime (large).
+
 Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] [--no-batch] [--no-grad]
+                       [--no-dao] [--no-large] [--cache-dir DIR]
        python bench.py --profile copy            one 1 GiB device copy, repeated (counter calibration)
        python bench.py --profile iters --iters K one graph-engine solve of K iterations (kernel counters)
-       python bench.py --large [--cache-dir DIR] the 1,000-node two-level WAN (~1M demands, ~4M paths):
-                                                 per-iteration kernel times, roofline, parity at K=16
+       python bench.py --profile batch --iters K the 512 failure scenarios in one launch (kernel counters)
+       python bench.py --large [--cache-dir DIR] only the 1,000-node two-level WAN (~1M demands, ~4M
+                                                 paths): per-iteration kernel times and roofline
+       python bench.py --probe-sync              kernel boundaries against grid barriers on this GPU
 """
 from __future__ import annotations
 
@@ -186,7 +194,7 @@ def large_run(args, torch, te, W, dev):
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": int(b), "avg_launch_us": round(ms * 1e3, 2)}
     log(f"kernels: {rl}")
     o64 = te.Options(fixed_iters=64, project=False, engine=te.ENGINE_GRAPH)
-    prob.solve(o64, stats=False)
+    _, _, st64 = prob.solve(o64)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prob.solve(o64, stats=False)
@@ -195,8 +203,10 @@ def large_run(args, torch, te, W, dev):
     out = {"workload": "two-level WAN: 50 Waxman regions x 20 nodes + backbone over 4 gateways/region, "
                        "all ordered pairs, 1+Pareto(1.2) gravity weights, k=4 latency-shortest paths",
            "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
-           "ms_per_iteration": round(ms_iter, 4), "roofline": rl}
-    print(json.dumps(out), flush=True)
+           "ms_per_iteration": round(ms_iter, 4), "demand_paths_per_lane": st64["paths_per_lane"],
+           "hop_slots": prob.info()["hop_slots"], "roofline": rl}
+    del prob
+    return out
 
 
 def main():
@@ -208,6 +218,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-dao", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--n-scen", type=int, default=512)
     ap.add_argument("--profile", choices=["copy", "iters", "batch"], default=None)
     ap.add_argument("--probe-sync", action="store_true")
@@ -235,7 +246,7 @@ def main():
         profile_run(args, torch, te, W, dev)
         return
     if args.large:
-        large_run(args, torch, te, W, dev)
+        print(json.dumps(large_run(args, torch, te, W, dev)), flush=True)
         return
     if args.probe_sync:
         probe_sync(torch, te, W, dev)
@@ -524,6 +535,12 @@ def main():
                 "grad_over_recorded_solve": round(t_grad / t_fwd, 3)}
         log(f"grad: {grad}")
 
+    # ---- the 1,000-node instance: where the per-iteration kernels are in the bandwidth regime ----
+    large = None
+    if not args.no_large:
+        large = large_run(args, torch, te, W, dev)
+        log(f"large: {large}")
+
     out = {
         "metric": METRIC,
         "value": round(ms_per_step, 4),
@@ -548,6 +565,7 @@ def main():
         "batched": batch,
         "grad": grad,
         "dao": dao_res,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
 
