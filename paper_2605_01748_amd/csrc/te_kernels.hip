@@ -399,14 +399,19 @@ __device__ __forceinline__ int csc_path(uint16_t v) { return v & 0x7fff; }
 // Segmented sums over the CSC entries of the non-empty links owned by this workgroup (ranks k0..):
 // acc[k - k0] += sum of vals[path] over the entries of link nzlink[k].  Each wavefront walks its
 // contiguous part wt = {first entry, end, rank of the link holding the first entry} of the
-// workgroup's entries in coalesced rows of 64; runs of equal link in a row are reduced by a
-// segmented scan and their tail lane adds one partial into the LDS accumulator.
+// workgroup's entries in coalesced rows of 64.  A full row in which no link starts belongs wholly
+// to the current link: each lane just adds its entry to a carried share (one add instead of a
+// scan; most rows, since links hold hundreds to thousands of entries).  A row in which a link
+// starts, or the part's last row, first hands the carried share in (wavefront sum, one LDS atomic),
+// then reduces its runs of equal link by a segmented scan whose tail lanes add one partial each.
 template <class I, class T>
 __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0, int4 wt, double *acc) {
   const int lane = threadIdx.x & 63;
   const int ja = wt.x, jb = wt.y;
   if (ja >= jb) return;
   int kbase = wt.z;
+  double carry = 0.0;    // this lane's share of link kbase over full rows in which no link starts
+  bool carried = false;  // wavefront-uniform
   constexpr int U = 4;  // rows whose loads are issued together
   for (int j = ja; j < jb; j += 64 * U) {
     I v[U];
@@ -427,6 +432,17 @@ __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0
       const bool valid = jj < jb;
       const bool head = valid && csc_head(v[u]) && jj != ja;
       const uint64_t hm = __ballot(head);
+      if (hm == 0ull && j + 64 * u + 63 < jb) {  // the whole row belongs to link kbase
+        carry += val[u];
+        carried = true;
+        continue;
+      }
+      if (carried) {  // the carried share goes in before the row's runs
+        const double cs = wave_sum_d(carry);
+        if (lane == 0) atomicAdd(&acc[kbase - k0], cs);
+        carry = 0.0;
+        carried = false;
+      }
       const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
       // segment key: rank of the entry's link; lanes past the end get -3 (after every valid lane)
       const int key = valid ? kbase + __popcll(hm & le) : -3;
@@ -435,6 +451,10 @@ __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0
       if (tail) atomicAdd(&acc[key - k0], x);
       kbase += __popcll(hm);
     }
+  }
+  if (carried) {
+    const double cs = wave_sum_d(carry);
+    if (lane == 0) atomicAdd(&acc[kbase - k0], cs);
   }
 }
 
