@@ -591,12 +591,25 @@ __global__ void kp_clamp_sums_in(Prob p, const float *x_in, double scale, ProjBu
   }
 }
 
+// one wavefront per link; lane l sums entries l, l + 64, ... in that order, four entries' loads
+// issued together
 __global__ void kp_loads(Prob p, ProjBuf b) {
   const int w = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   const int nw = (gridDim.x * blockDim.x) >> 6;
   for (int e = w; e < p.E; e += nw) {
     double acc = 0.0;
-    for (int j = p.lptr[e] + lane; j < p.lptr[e + 1]; j += 64) acc += b.xd[p.lpaths[j]];
+    const int j1 = p.lptr[e + 1];
+    for (int j = p.lptr[e] + lane; j < j1; j += 256) {
+      int r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) r[u] = j + 64 * u < j1 ? p.lpaths[j + 64 * u] : -1;
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = r[u] >= 0 ? b.xd[r[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r[u] >= 0) acc += v[u];
+    }
     acc = wave_sum_d(acc);
     if (lane == 0) b.L[e] = acc;
   }
@@ -604,21 +617,23 @@ __global__ void kp_loads(Prob p, ProjBuf b) {
 
 // C_p = number of violated links on p, and the log score
 // alpha of the scores: the solve's final alpha (fin) or, with fin null, the given one
+// one lane per path (G lanes per demand, as in the demand kernel): the number of violated links on
+// the path and its log score
 __global__ void kp_counts(Prob p, ProjBuf b, const Ctrl *fin, double alpha_in) {
   const float alpha = (float)(fin ? fin->alpha : alpha_in);
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int nth = gridDim.x * blockDim.x;
-  for (int c = tid; c < p.D; c += nth) {
-    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
-      int k = 0;
-      for (int i = p.pptr[r]; i < p.pptr[r + 1]; ++i) {
-        const int e = p.plinks[i];
-        k += b.L[e] > p.Cn[e];
-      }
-      b.Cp[r] = k;
-      b.lsc[r] = log_score(b.S[c], k, alpha);
-    }
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = t >> p.logG, lane = t & (p.G - 1);
+  if (c >= p.D) return;
+  const int r0 = p.dptr[c];
+  if (lane >= p.dptr[c + 1] - r0) return;
+  const int r = r0 + lane;
+  int k = 0;
+  for (int i = p.pptr[r]; i < p.pptr[r + 1]; ++i) {
+    const int e = p.plinks[i];
+    k += b.L[e] > p.Cn[e];
   }
+  b.Cp[r] = k;
+  b.lsc[r] = log_score(b.S[c], k, alpha);
 }
 
 // step 3: per demand, trim the excess over D_c from paths in descending score
@@ -1330,11 +1345,12 @@ hipError_t launch_finish(const State &s, const Params *prm, int last_par, hipStr
 // steps 2-5 of Algorithm 2 on the clamped working copy b.xd / b.S
 static void launch_trims(const Prob &p, const ProjBuf &b, const Ctrl *fin, double alpha, hipStream_t st) {
   const int nD = (p.D + 255) / 256, nE = (p.E * 64 + 255) / 256;
+  const int nC = (int)(((int64_t)p.D * p.G + 255) / 256);  // one lane per path slot
   hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
-  hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin, alpha);
+  hipLaunchKernelGGL(kp_counts, dim3(nC), dim3(256), 0, st, p, b, fin, alpha);
   hipLaunchKernelGGL(kp_demand_trim, dim3(nD), dim3(256), 0, st, p, b);
   hipLaunchKernelGGL(kp_loads, dim3(nE), dim3(256), 0, st, p, b);
-  hipLaunchKernelGGL(kp_counts, dim3(nD), dim3(256), 0, st, p, b, fin, alpha);
+  hipLaunchKernelGGL(kp_counts, dim3(nC), dim3(256), 0, st, p, b, fin, alpha);
   int nl = p.E < 4096 ? p.E : 4096;
   hipLaunchKernelGGL(kp_link_trim, dim3(nl > 0 ? nl : 1), dim3(256), 0, st, p, b);
 }
