@@ -80,7 +80,7 @@ struct State {
   double *udem, *S;  // [D] demand duals and last root of the sum equation
   double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
   Ctrl *ctrl;        // [3]
-  double *partA;     // [2][nA][4]
+  double *partA;     // [2][nA * waves per workgroup][4]: the demand kernels' per-wavefront rows
   double *partB;     // [2][nB][4]
   int32_t nA, nB;
   double *log_beta;  // nullable [log_cap]: (beta_k, alpha_k) actually used, written when recording

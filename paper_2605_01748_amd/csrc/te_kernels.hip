@@ -71,6 +71,20 @@ __device__ __forceinline__ void finish_ctrl(CtrlPrefetch &cp, const Params &prm,
   if (threadIdx.x == 0) *out = decide(cp.prev, cp.v, prm);
 }
 
+// per-wavefront partial sums (sum, sum, -, max) into dst[4 w .. 4 w + 3] by the wavefront's lane 0
+__device__ __forceinline__ void wave_partials(double a, double b, double d, double *dst) {
+  a = wave_sum_d(a);
+  b = wave_sum_d(b);
+  d = wave_max_d(d);
+  if ((threadIdx.x & 63) == 0) {
+    double *o = dst + (threadIdx.x >> 6) * 4;
+    o[0] = a;
+    o[1] = b;
+    o[2] = -INFINITY;
+    o[3] = d;
+  }
+}
+
 // XCD-aware work order.  The dispatcher deals the workgroups of a launch round-robin over the 8
 // XCDs (workgroup b runs on XCD b % 8, each XCD with its own L2).  Processing logical block
 // xcd_chunk(b) instead of b gives every XCD one contiguous range of the logical work: the demand
@@ -291,7 +305,7 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
       dem_v = (Ssum - dm.D) / dm.D;
     }
   }
-  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + bl) * 4);
+  wave_partials(ds2, dr2, dem_v, s.partA + ((size_t)par * s.nA + bl) * (kThreads / 64) * 4);
 }
 
 // The same step with PPL (2, 4 or 8) paths per lane, for instances large enough to be bound by
@@ -386,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
       dem_v = (Ssum - dm.D) / dm.D;
     }
   }
-  block_partials(ds2, dr2, -INFINITY, dem_v, s.partA + ((size_t)par * s.nA + bl) * 4);
+  wave_partials(ds2, dr2, dem_v, s.partA + ((size_t)par * s.nA + bl) * (kThreads / 64) * 4);
 }
 
 // CSC entry encodings: int32 (graph engine) with bit 31 on a link's first entry, uint16 (workgroup
@@ -489,9 +503,9 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     C_f = p.Cn[e_f];
   }
   double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
-  if (w == 1) {  // fold the demand kernel's rows b, b + nB, ... (fixed order)
-    const double *pa = s.partA + (size_t)par * s.nA * 4;
-    for (int i = bl + lane * gridDim.x; i < s.nA; i += 64 * gridDim.x) {
+  if (w == 1) {  // fold the demand kernel's per-wavefront rows b, b + nB, ... (fixed order)
+    const double *pa = s.partA + (size_t)par * s.nA * (kThreads / 64) * 4;
+    for (int i = bl + lane * gridDim.x; i < s.nA * (kThreads / 64); i += 64 * gridDim.x) {
       a0 += pa[4 * i + 0];
       a1 += pa[4 * i + 1];
       a3 = fmax(a3, pa[4 * i + 3]);

@@ -550,7 +550,7 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
             dalloc(&c->d_Cn, c->E) == hipSuccess && alloc_fwd(c->work, c) == hipSuccess &&
             dalloc(&c->st.xf, c->P) == hipSuccess &&
-            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA1 * 4) == hipSuccess &&
+            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA1 * (kThreads / 64) * 4) == hipSuccess &&
             dalloc(&c->st.partB, (size_t)2 * nB * 4) == hipSuccess &&
             dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
             dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
