@@ -867,7 +867,8 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
   double *uneg = x + P;                              // P
   double *Dn = uneg + P;                             // D
   // 16-bit indices (the host admits only instances with P < 2^15 and nnz, E, D < 2^16 here)
-  uint16_t *pptr = (uint16_t *)(Dn + D);             // P + 1
+  double *Sp = Dn + D;                               // D: the root before the last one
+  uint16_t *pptr = (uint16_t *)(Sp + D);             // P + 1
   uint16_t *plinks = pptr + P + 1;                   // nnz
   uint16_t *dptr = plinks + nnz;                     // D + 1
   uint16_t *lptr = dptr + D + 1;                     // E + 1
@@ -902,6 +903,7 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
     }
     udem[c] = 0.0;
     S[c] = sum;
+    Sp[c] = sum;
   }
   if (tid == 0) cs = initial_ctrl(prm);
   __syncthreads();
@@ -956,7 +958,13 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
         dm.D = Dn[c];
         dm.u = udem[c] * inv_f;
         int steps;
-        const double Sst = sum_root(S[c], L, dm, Gp, &steps);
+        const double Sk = S[c];
+        // the root solve starts from the linear extrapolation of the last two roots (fewer
+        // evaluations than from the last root: with up to 64 demands per wavefront the slowest
+        // demand decides a wavefront's time)
+        double Sstart = Sk + (Sk - Sp[c]);
+        if (dm.alpha > 0.0 && !(Sstart > 0.0)) Sstart = Sk;
+        const double Sst = sum_root(Sstart, L, dm, Gp, &steps);
         const double h = h_of(Sst, dm);
         double xsum = 0.0;
 #pragma unroll
@@ -977,6 +985,7 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
         if (lane == 0) {
           const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
           udem[c] = ud;
+          Sp[c] = Sk;
           S[c] = Sst;
           dr2 += (ud - dm.u) * (ud - dm.u);
           dem_v = fmax(dem_v, (Ssum - dm.D) / dm.D);
@@ -1429,7 +1438,7 @@ hipError_t launch_block_solve(const BatchDesc *descs, int n, const Pools &pools,
 // 16-bit LDS encoding (P < 2^15 for the head bit, nnz, E, D < 2^16).
 size_t block_lds_bytes(int E, int P, int D, int nnz) {
   if (P >= 32768 || nnz >= 65536 || E >= 65536 || D >= 65536) return SIZE_MAX;
-  return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 8) + (size_t)P * 8 * 2 +
+  return (size_t)E * (16 + 8 + 8) + (size_t)D * (8 + 8 + 8 + 8) + (size_t)P * 8 * 2 +
          (size_t)2 * ((P + 1) + nnz + (D + 1) + (E + 1) + nnz + E) + 16;
 }
 
