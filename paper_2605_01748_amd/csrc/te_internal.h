@@ -79,6 +79,10 @@ struct State {
   float *xf;         // [P] FP32 copy of x, read by the link kernel's gathers (half the bytes)
   double *udem, *S;  // [D] demand duals and last root of the sum equation
   double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
+  // where an iteration writes its new x, u_neg, u_dem, S and (g, q): the arrays above (in place),
+  // or another state block (the gradient's recomputation writes iteration k + 1 next to k)
+  double *xo, *unego, *udemo, *So;
+  double2 *gqo;
   Ctrl *ctrl;        // [3]
   double *partA;     // [2][nA * waves per workgroup][4]: the demand kernels' per-wavefront rows
   double *partB;     // [2][nB][4]

@@ -291,16 +291,16 @@ __global__ __launch_bounds__(kThreads) void k_demand(Prob p, State s, const Para
     const double Ssum = group_sum_d(xn, G);
     if (L.on) {
       const double un = fmax(L.un - xn, 0.0);
-      s.x[r] = xn;
+      s.xo[r] = xn;
       s.xf[r] = (float)xn;
-      s.uneg[r] = un;
+      s.unego[r] = un;
       ds2 = (xn - xr) * (xn - xr);
       dr2 = (un - L.un) * (un - L.un);
     }
     if (lane == 0) {
       const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
-      s.udem[c] = ud;
-      s.S[c] = Sst;
+      s.udemo[c] = ud;
+      s.So[c] = Sst;
       dr2 += (ud - dm.u) * (ud - dm.u);
       dem_v = (Ssum - dm.D) / dm.D;
     }
@@ -384,9 +384,9 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
       const double b = L.a[j] - h;
       const double xn = (b >= L.n[j] * L.un[j]) ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
       const double un = fmax(L.un[j] - xn, 0.0);
-      s.x[r] = xn;
+      s.xo[r] = xn;
       s.xf[r] = (float)xn;
-      s.uneg[r] = un;
+      s.unego[r] = un;
       xsum += xn;
       ds2 += (xn - xr[j]) * (xn - xr[j]);
       dr2 += (un - L.un[j]) * (un - L.un[j]);
@@ -394,8 +394,8 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
     const double Ssum = group_sum_d(xsum, Gp);
     if (lane == 0) {
       const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
-      s.udem[c] = ud;
-      s.S[c] = Sst;
+      s.udemo[c] = ud;
+      s.So[c] = Sst;
       dr2 += (ud - dm.u) * (ud - dm.u);
       dem_v = (Ssum - dm.D) / dm.D;
     }
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     const double load = acc[k - k0];
     const double gold = v.x * inv_f;
     const double gn = fmax(gold + (load - Ce) / (double)(1 + ne), 0.0);
-    s.gq[e] = make_double2(gn, gold - gn);
+    s.gqo[e] = make_double2(gn, gold - gn);
     dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
     cap_v = fmax(cap_v, (load - Ce) / Ce);
   }

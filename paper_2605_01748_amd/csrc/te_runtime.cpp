@@ -558,11 +558,11 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
             dalloc(&c->d_params, 1) == hipSuccess && dalloc(&c->d_desc, 1) == hipSuccess &&
             dalloc(&c->d_bout, 1) == hipSuccess && dalloc(&c->d_wtab, wtab.size()) == hipSuccess;
   if (!ok) return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
-  c->st.x = c->work.x;
-  c->st.uneg = c->work.uneg;
-  c->st.udem = c->work.udem;
-  c->st.S = c->work.S;
-  c->st.gq = c->work.gq;
+  c->st.x = c->st.xo = c->work.x;
+  c->st.uneg = c->st.unego = c->work.uneg;
+  c->st.udem = c->st.udemo = c->work.udem;
+  c->st.S = c->st.So = c->work.S;
+  c->st.gq = c->st.gqo = c->work.gq;
   if (hipMemcpy(c->d_wtab, wtab.data(), sizeof(int4) * wtab.size(), hipMemcpyHostToDevice) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the link work table failed"));
   if (hipHostMalloc((void **)&c->h_params, sizeof(Params)) != hipSuccess ||
@@ -921,20 +921,29 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   te_status s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
-  const FwdState work = c->work;
   c->state_scale = 0.0;  // the segment recomputation overwrites the state a warm restart would continue from
   // reverse, segment by segment: restore the segment's checkpoint, recompute its iterations with
   // the recorded schedule keeping every state, then run the adjoint iterations backwards
   HIPCHK(launch_adj_seed(c->prob, a, dS_dev, stream));
   for (int sgi = nck - 1; sgi >= 0; --sgi) {
     const int k0 = sgi * ck, k1 = std::min(K, k0 + ck);
-    HIPCHK(copy_fwd(work, c->ckpt[sgi], c, stream));
+    HIPCHK(copy_fwd(c->seg[0], c->ckpt[sgi], c, stream));
     HIPCHK(hipMemcpyAsync(c->st.ctrl + ((k0 + 1) & 1), c->ckpt_ctrl[sgi], sizeof(Ctrl), hipMemcpyDeviceToDevice,
                           stream));
-    HIPCHK(copy_fwd(c->seg[0], work, c, stream));
-    for (int k = k0; k < k1; ++k) {
-      HIPCHK(launch_iteration(c->prob, c->st, c->d_params, k & 1, stream));
-      HIPCHK(copy_fwd(c->seg[k - k0 + 1], work, c, stream));
+    for (int k = k0; k < k1; ++k) {  // iteration k reads state k - k0 and writes state k - k0 + 1
+      State sk = c->st;
+      const FwdState &fi = c->seg[k - k0], &fo = c->seg[k - k0 + 1];
+      sk.x = fi.x;
+      sk.uneg = fi.uneg;
+      sk.udem = fi.udem;
+      sk.S = fi.S;
+      sk.gq = fi.gq;
+      sk.xo = fo.x;
+      sk.unego = fo.uneg;
+      sk.udemo = fo.udem;
+      sk.So = fo.S;
+      sk.gqo = fo.gq;
+      HIPCHK(launch_iteration(c->prob, sk, c->d_params, k & 1, stream));
     }
     for (int k = k1 - 1; k >= k0; --k) {
       const double rho = k > 0 ? lb[k - 1] / lb[k] : 1.0;
