@@ -483,6 +483,7 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
   __shared__ double acc[kMaxLinksPerBlock];
+  __shared__ double fold[3];
   CtrlPrefetch cp;
   if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -510,6 +511,14 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
       a1 += pa[4 * i + 1];
       a3 = fmax(a3, pa[4 * i + 3]);
     }
+    a0 = wave_sum_d(a0);
+    a1 = wave_sum_d(a1);
+    a3 = wave_max_d(a3);
+    if (lane == 0) {
+      fold[0] = a0;
+      fold[1] = a1;
+      fold[2] = a3;
+    }
   }
   __syncthreads();
   seg_rows_sum(p.lpf, s.xf, k0, wt, acc);
@@ -527,6 +536,29 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   if (cs.stop) return;
   const double inv_f = cs.inv_f;
   double dr2 = 0.0, cap_v = -INFINITY;
+  if (k1 - k0 <= 64) {
+    // at most 64 links: the first wavefront updates them all and writes the workgroup's row
+    // itself, without a second barrier
+    if (threadIdx.x >= 64) return;
+    if (kf < k1) {
+      const double load = acc[kf - k0];
+      const double gold = gq_f.x * inv_f;
+      const double gn = fmax(gold + (load - C_f) / (double)(1 + ne_f), 0.0);
+      s.gqo[e_f] = make_double2(gn, gold - gn);
+      dr2 = (double)(1 + ne_f) * (gn - gold) * (gn - gold);
+      cap_v = (load - C_f) / C_f;
+    }
+    dr2 = wave_sum_d(dr2);
+    cap_v = wave_max_d(cap_v);
+    if (lane == 0) {
+      double *o = s.partB + ((size_t)par * s.nB + bl) * 4;
+      o[0] = fold[0];
+      o[1] = dr2 + fold[1];
+      o[2] = cap_v;
+      o[3] = fold[2];
+    }
+    return;
+  }
   for (int k = kf; k < k1; k += blockDim.x) {
     int e = e_f, ne = ne_f;
     double2 v = gq_f;
@@ -544,7 +576,9 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
     cap_v = fmax(cap_v, (load - Ce) / Ce);
   }
-  block_partials(a0, dr2 + a1, cap_v, a3, s.partB + ((size_t)par * s.nB + bl) * 4);
+  const bool t0 = threadIdx.x == 0;
+  block_partials(t0 ? fold[0] : 0.0, dr2 + (t0 ? fold[1] : 0.0), cap_v, t0 ? fold[2] : -INFINITY,
+                 s.partB + ((size_t)par * s.nB + bl) * 4);
 }
 
 // Final control record: applies the decision pending after the last iteration.
