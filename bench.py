@@ -22,6 +22,8 @@ Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--no-cpu-baseline] 
        python bench.py --profile copy            one 1 GiB device copy, repeated (counter calibration)
        python bench.py --profile iters --iters K one graph-engine solve of K iterations (kernel counters)
        python bench.py --profile batch --iters K the 512 failure scenarios in one launch (kernel counters)
+       python bench.py --profile iters-large --iters K
+                                                 the same on the 1,000-node instance (--cache-dir)
        python bench.py --large [--cache-dir DIR] only the 1,000-node two-level WAN (~1M demands, ~4M
                                                  paths): per-iteration kernel times and roofline
        python bench.py --probe-sync              kernel boundaries against grid barriers on this GPU
@@ -136,7 +138,7 @@ def profile_run(args, torch, te, W, dev):
         log(f"batch of {len(scen)}, {args.iters} iterations, {st[0]['block_threads']} threads, "
             f"{st[0]['paths_per_lane']} paths per lane: {(time.perf_counter() - t) * 1e3:.3f} ms")
         return
-    inst = W.waxman150(0)
+    inst = W.two_level1000(0, cache_dir=args.cache_dir) if args.profile == "iters-large" else W.waxman150(0)
     log(inst.summary())
     prob = te.Problem(inst)
     o = te.Options(fixed_iters=args.iters, project=False, engine=te.ENGINE_GRAPH)
@@ -220,7 +222,7 @@ def main():
     ap.add_argument("--no-dao", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--n-scen", type=int, default=512)
-    ap.add_argument("--profile", choices=["copy", "iters", "batch"], default=None)
+    ap.add_argument("--profile", choices=["copy", "iters", "iters-large", "batch"], default=None)
     ap.add_argument("--probe-sync", action="store_true")
     ap.add_argument("--iters", type=int, default=64)
     ap.add_argument("--block-threads", type=int, default=0)
