@@ -46,7 +46,13 @@ class _Options(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("adapt_beta", ctypes.c_int32), ("project", ctypes.c_int32),
                 ("collapsed", ctypes.c_int32), ("sched_beta", ctypes.c_void_p), ("sched_alpha", ctypes.c_void_p),
                 ("sched_len", ctypes.c_int32), ("root_max_steps", ctypes.c_int32),
-                ("dual_res_scaled", ctypes.c_int32), ("beta_every", ctypes.c_int32)]
+                ("dual_res_scaled", ctypes.c_int32), ("beta_every", ctypes.c_int32), ("warm", ctypes.c_void_p)]
+
+
+class _Warm(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("S", ctypes.c_void_p), ("y", ctypes.c_void_p), ("ucon", ctypes.c_void_p),
+                ("ucap", ctypes.c_void_p), ("udem", ctypes.c_void_p), ("uneg", ctypes.c_void_p),
+                ("beta", ctypes.c_double), ("alpha", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -83,7 +89,7 @@ def _load():
                                          ctypes.c_int, P, P, P, P, P, P]
         lib.gate_oracle_project.restype = ctypes.c_int
         lib.gate_oracle_project.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P, P,
-                                            ctypes.c_double, P]
+                                            ctypes.c_double, P, P, P]
         _lib = lib
     return _lib
 
@@ -140,13 +146,24 @@ class Result:
     def schedule(self):
         return self.trace[:, 1].copy(), self.trace[:, 0].copy()
 
+    def warm_state(self):
+        """The iterate this solve left (unprojected rates, last sums, rate suggestions, every scaled
+        dual, the penalty and alpha), in caller units: the `warm` input of a later solve."""
+        if self.dual_dem is None:
+            raise ValueError("solve(..., want_state=True) keeps the duals")
+        s = self.scale
+        return dict(x=self.x_raw * s, S=self.S_raw * s, y=self.y * s, ucon=self.dual_con * s,
+                    ucap=self.dual_cap * s, udem=self.dual_dem * s, uneg=self.dual_neg * s,
+                    beta=self.beta, alpha=self.final_alpha)
+
 
 def _p(a):
     return None if a is None else a.ctypes.data
 
 
-def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True) -> Result:
-    """Run the oracle on a workloads.Instance."""
+def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, warm=None) -> Result:
+    """Run the oracle on a workloads.Instance.  warm: a state from Result.warm_state() (caller units)
+    to continue from instead of initialising (x0 is then ignored)."""
     opts = opts or Options()
     lib = _load()
     E, P, D, nnz = inst.n_links, inst.n_paths, inst.n_demands, inst.nnz
@@ -196,6 +213,19 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True) -
         st.dual_dem, st.dual_cap, st.dual_neg, st.dual_con, st.y = (dd.ctypes.data, dc.ctypes.data, dn.ctypes.data,
                                                                     dcon.ctypes.data, yy.ctypes.data)
     x0a = None if x0 is None else np.ascontiguousarray(x0, np.float64)
+    wkeep = []
+    if warm is not None:
+        w = _Warm()
+        for name, n in (("x", P), ("S", D), ("y", nnz), ("ucon", nnz), ("ucap", E), ("udem", D), ("uneg", P)):
+            a = np.ascontiguousarray(warm[name], np.float64)
+            if a.shape != (n,):
+                raise ValueError(f"warm[{name!r}] has shape {a.shape}, expected ({n},)")
+            wkeep.append(a)
+            setattr(w, name, a.ctypes.data)
+        w.beta = float(warm["beta"])
+        w.alpha = float(warm["alpha"])
+        wkeep.append(w)
+        o.warm = ctypes.addressof(w)
     stats = _Stats()
     rc = lib.gate_oracle_solve(E, cap.ctypes.data, P, pptr.ctypes.data, plinks.ctypes.data, D, dptr.ctypes.data,
                                dem.ctypes.data, ctypes.byref(o), _p(x0a), x_out.ctypes.data, S_out.ctypes.data,
@@ -224,18 +254,22 @@ def sum_root(a, n_links, uneg, D, udem, alpha, beta, S0):
     return S.value, x, steps
 
 
-def project(inst, x, alpha):
-    """Algorithm 2 on rates x (original units); returns the projected copy."""
+def project(inst, x, alpha, stages: bool = False):
+    """Algorithm 2 on rates x (original units); returns the projected copy, or with stages=True
+    (projected, rates after the demand trims, log-scores of the link phase)."""
     lib = _load()
     xx = np.array(x, dtype=np.float64, copy=True)
+    xm = np.zeros_like(xx) if stages else None
+    sc = np.zeros_like(xx) if stages else None
     cap = np.ascontiguousarray(inst.capacity, np.float64)
     pptr = np.ascontiguousarray(inst.path_ptr, np.int64)
     plinks = np.ascontiguousarray(inst.path_links, np.int32)
     dptr = np.ascontiguousarray(inst.demand_path_ptr, np.int32)
     dem = np.ascontiguousarray(inst.demand, np.float64)
     lib.gate_oracle_project(inst.n_links, cap.ctypes.data, inst.n_paths, pptr.ctypes.data, plinks.ctypes.data,
-                            inst.n_demands, dptr.ctypes.data, dem.ctypes.data, float(alpha), xx.ctypes.data)
-    return xx
+                            inst.n_demands, dptr.ctypes.data, dem.ctypes.data, float(alpha), xx.ctypes.data,
+                            _p(xm), _p(sc))
+    return (xx, xm, sc) if stages else xx
 
 
 def used_scale(inst):

@@ -58,6 +58,23 @@
 #define GO_HIT_BETA_BOUND 8
 #define GO_NUMERIC 16
 
+/* Optional warm state: the whole iterate an earlier solve left (Algorithm 1 takes x^0 and beta as
+ * optional inputs; here every dual, the last sums and alpha come along, as when a solve is continued
+ * after the network state changed).  Caller units: every array is divided by this solve's scale s,
+ * i.e. the scaled duals, which have the units of rates, are converted like the rates.  All pointers
+ * are required. */
+typedef struct {
+  const double *x;     /* [P] rates */
+  const double *S;     /* [D] last sums (start of the root solve) */
+  const double *y;     /* [nnz] rate suggestions, CSR incidence order */
+  const double *ucon;  /* [nnz] consensus duals, CSR incidence order */
+  const double *ucap;  /* [E] */
+  const double *udem;  /* [D] */
+  const double *uneg;  /* [P] */
+  double beta;         /* penalty the duals are scaled for */
+  double alpha;        /* fairness reached (capped at alpha_target) */
+} go_warm;
+
 typedef struct {
   double alpha_target; /* INFINITY = max-min fairness */
   double gamma;        /* residual threshold */
@@ -76,6 +93,7 @@ typedef struct {
   int32_t root_max_steps;    /* Newton-bisection step cap (default 200) */
   int32_t dual_res_scaled;   /* 1: s = beta * ||x^{k+1} - x^k||, 0: as printed, without beta */
   int32_t beta_every;        /* apply the residual-balancing rule after every T-th sweep (READING) */
+  const go_warm *warm;       /* nullable: continue from this state instead of initialising */
 } go_options;
 
 typedef struct {
@@ -267,12 +285,11 @@ static int trim_cmp(const void *A, const void *B) {
   return (a->p > b->p) ? -1 : (a->p < b->p ? 1 : 0);
 }
 
-/* log of score_p = S_c^alpha * C_p; -inf when C_p = 0 or S_c = 0.  The score only orders paths
-   (a discrete decision); the paper fixes no precision for it, so it is taken in single precision,
-   as the GPU path computes it, and the two sides order near-equal scores alike. */
+/* log of score_p = S_c^alpha * C_p (Algorithm 2); -inf when C_p = 0 or S_c = 0.  The paper fixes
+   no precision for the score, so it is taken in FP64 like everything else here. */
 static double log_score(double S, int Cp, double alpha) {
   if (Cp <= 0 || !(S > 0.0)) return -INFINITY;
-  return (double)((float)alpha * logf((float)S) + logf((float)Cp));
+  return alpha * log(S) + log((double)Cp);
 }
 
 static void aux_vars(int E, const double *C, int P, const int64_t *pptr, const int32_t *plinks, int D,
@@ -295,9 +312,11 @@ static void aux_vars(int E, const double *C, int P, const int64_t *pptr, const i
   (void)Dem;
 }
 
+/* x_mid (nullable): the rates after the demand trims (step 3); score (nullable): the log-scores of
+   the link phase (after the recompute of step 4). */
 static void project(int E, const double *C, int P, const int64_t *pptr, const int32_t *plinks, int D,
                     const int32_t *dptr, const double *Dem, const int32_t *lptr, const int32_t *lpaths,
-                    double alpha, double *x) {
+                    double alpha, double *x, double *x_mid, double *score) {
   double *S = (double *)malloc(sizeof(double) * (size_t)(D ? D : 1));
   double *L = (double *)malloc(sizeof(double) * (size_t)E);
   double *Vv = (double *)malloc(sizeof(double) * (size_t)E);
@@ -328,12 +347,14 @@ static void project(int E, const double *C, int P, const int64_t *pptr, const in
   }
   /* 4. recompute auxiliary variables */
   aux_vars(E, C, P, pptr, plinks, D, dptr, Dem, x, S, L, Vv, Cp);
+  int *dem_of = (int *)malloc(sizeof(int) * (size_t)(P ? P : 1));
+  for (int c = 0; c < D; ++c) for (int r = dptr[c]; r < dptr[c + 1]; ++r) dem_of[r] = c;
+  if (x_mid) memcpy(x_mid, x, sizeof(double) * (size_t)P);
+  if (score) for (int r = 0; r < P; ++r) score[r] = log_score(S[dem_of[r]], Cp[r], alpha);
   /* 5. capacity violations.  READING: every link trims from the same
    * snapshot of x ("in parallel" in Algorithm 2); a path trimmed by several
    * links gives up the largest of those trims. */
   double *trim = (double *)calloc((size_t)(P ? P : 1), sizeof(double));
-  int *dem_of = (int *)malloc(sizeof(int) * (size_t)(P ? P : 1));
-  for (int c = 0; c < D; ++c) for (int r = dptr[c]; r < dptr[c + 1]; ++r) dem_of[r] = c;
   for (int e = 0; e < E; ++e) {
     double Ve = Vv[e];
     if (!(Ve > 0.0)) continue;
@@ -353,10 +374,10 @@ static void project(int E, const double *C, int P, const int64_t *pptr, const in
   free(trim); free(dem_of); free(it); free(S); free(L); free(Vv); free(Cp);
 }
 
-/* Exported for pins: Algorithm 2 on given rates (original units). */
+/* Exported for pins: Algorithm 2 on given rates (original units); x_mid / score as in project(). */
 int gate_oracle_project(int n_links, const double *capacity, int n_paths, const int64_t *path_ptr,
                         const int32_t *path_links, int n_demands, const int32_t *demand_path_ptr,
-                        const double *demand, double alpha, double *x) {
+                        const double *demand, double alpha, double *x, double *x_mid, double *score) {
   int E = n_links, P = n_paths;
   int32_t *lptr = (int32_t *)calloc((size_t)E + 1, sizeof(int32_t));
   for (int64_t i = 0; i < path_ptr[P]; ++i) lptr[path_links[i] + 1]++;
@@ -366,7 +387,8 @@ int gate_oracle_project(int n_links, const double *capacity, int n_paths, const 
   int32_t *lpaths = (int32_t *)malloc(sizeof(int32_t) * (size_t)(path_ptr[P] ? path_ptr[P] : 1));
   for (int r = 0; r < P; ++r)
     for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) lpaths[fill[path_links[i]]++] = r;
-  project(E, capacity, P, path_ptr, path_links, n_demands, demand_path_ptr, demand, lptr, lpaths, alpha, x);
+  project(E, capacity, P, path_ptr, path_links, n_demands, demand_path_ptr, demand, lptr, lpaths, alpha, x,
+          x_mid, score);
   free(lptr); free(fill); free(lpaths);
   return 0;
 }
@@ -431,26 +453,50 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   double *de = (double *)malloc(sizeof(double) * (size_t)E);
   int *steps_c = (int *)calloc((size_t)(D ? D : 1), sizeof(int));
 
-  for (int c = 0; c < D; ++c) {
-    int m = demand_path_ptr[c + 1] - demand_path_ptr[c];
-    for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r)
-      x[r] = x0 ? x0[r] / scale : Dm[c] / m; /* x^0 = D/|P_st| unless given */
+  const go_warm *wm = opt->warm;
+  if (wm) {
+    /* continuation: the earlier iterate, converted to this solve's units */
+    for (int r = 0; r < P; ++r) { x[r] = wm->x[r] / scale; uneg[r] = wm->uneg[r] / scale; }
+    for (int c = 0; c < D; ++c) { S[c] = wm->S[c] / scale; udem[c] = wm->udem[c] / scale; }
+    for (int64_t i = 0; i < nnz; ++i) { y[i] = wm->y[i] / scale; ucon[i] = wm->ucon[i] / scale; }
+    for (int e = 0; e < E; ++e) ucap[e] = wm->ucap[e] / scale;
+    /* collapsed bookkeeping: g_e = dual_cap_e and q_e = y_{e,r} - x_r (the same for every r on e
+       once a sweep has run) */
+    for (int e = 0; e < E; ++e) {
+      gq_g[e] = ucap[e];
+      gq_q[e] = lptr[e + 1] > lptr[e] ? y[linc[lptr[e]]] - x[inc_path[linc[lptr[e]]]] : 0.0;
+    }
+  } else {
+    for (int c = 0; c < D; ++c) {
+      int m = demand_path_ptr[c + 1] - demand_path_ptr[c];
+      for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r)
+        x[r] = x0 ? x0[r] / scale : Dm[c] / m; /* x^0 = D/|P_st| unless given */
+    }
+    for (int c = 0; c < D; ++c) {
+      double s = 0.0;
+      for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r) s += x[r];
+      S[c] = s;
+    }
+    for (int r = 0; r < P; ++r)
+      for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) y[i] = x[r]; /* y^0 = x^0 */
   }
-  for (int c = 0; c < D; ++c) {
-    double s = 0.0;
-    for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r) s += x[r];
-    S[c] = s;
-  }
-  for (int r = 0; r < P; ++r)
-    for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) y[i] = x[r]; /* y^0 = x^0 */
 
   const int replay = opt->sched_beta != NULL && opt->sched_alpha != NULL;
   const int fixed = opt->fixed_iters > 0;
   const int K = fixed ? opt->fixed_iters : opt->max_iters;
   const int max_steps = opt->root_max_steps > 0 ? opt->root_max_steps : 200;
-  double alpha = replay ? opt->sched_alpha[0] : 0.0;
+  double alpha = replay ? opt->sched_alpha[0] : (wm ? wm->alpha : 0.0);
   if (!replay && opt->alpha_target < alpha) alpha = opt->alpha_target;
-  double beta = replay ? opt->sched_beta[0] : opt->beta0;
+  double beta = replay ? opt->sched_beta[0] : (wm ? wm->beta : opt->beta0);
+  if (wm && beta != wm->beta) {
+    /* a replayed schedule starting at another penalty: the scaled duals are divided by the
+       factor, as on every change of beta */
+    const double f0 = beta / wm->beta;
+    for (int c = 0; c < D; ++c) udem[c] /= f0;
+    for (int e = 0; e < E; ++e) { ucap[e] /= f0; gq_g[e] /= f0; }
+    for (int r = 0; r < P; ++r) uneg[r] /= f0;
+    for (int64_t i = 0; i < nnz; ++i) ucon[i] /= f0;
+  }
   int j = 0, k = 0, stop = 0;
   double r_res = 0.0, s_res = 0.0;
   long long steps_total = 0;
@@ -663,7 +709,7 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   }
 
   if (opt->project)
-    project(E, C, P, path_ptr, path_links, D, demand_path_ptr, Dm, lptr, lpaths, alpha, x);
+    project(E, C, P, path_ptr, path_links, D, demand_path_ptr, Dm, lptr, lpaths, alpha, x, NULL, NULL);
   for (int r = 0; r < P; ++r) x_out[r] = x[r] * scale;
   if (S_out)
     for (int c = 0; c < D; ++c) {
