@@ -77,6 +77,14 @@ enum {
   TE_ENGINE_BLOCK = 2  /* whole solve inside one workgroup, state resident in LDS */
 };
 
+/* te_options.link_sums */
+enum {
+  TE_LINK_SUMS_AUTO = 0,
+  TE_LINK_SUMS_PRIVATE = 1, /* every demand workgroup adds its paths' rates into its own copy of the link
+                               loads (LDS), rows reduced per link in a second kernel */
+  TE_LINK_SUMS_CSC = 2      /* segmented sums over the link -> path incidence list */
+};
+
 typedef struct {
   double alpha_target; /* fairness target: INFINITY = max-min (default), 0 = max-flow, 1 = proportional */
   double gamma;        /* residual threshold of the stop test (section 3.4); default 1e-3 */
@@ -116,6 +124,20 @@ typedef struct {
   const double *sched_beta;
   const double *sched_alpha;
   int32_t sched_len;
+  int32_t trace;       /* 1: log, for every iteration k, the beta_k and alpha_k it used and its residuals
+                          r_k, s_k (section 3.4), read back with te_trace (a recorded solve logs them
+                          anyway); te_solve only, either engine */
+  int32_t link_sums;   /* graph engine, how the link loads sum_{r on e} x_r are formed: TE_LINK_SUMS_*;
+                          0 (default): privatised for instances with at least 2^20 lane slots (demands x
+                          G) and at most 19,456 links, else CSC.
+                          A change recaptures the iteration graphs (after a device-wide synchronisation). */
+  int32_t per_link;    /* 1: per-link penalties (the conclusion's learning rates adaptive across parts of
+                          the topology, read as: link e's consensus and capacity constraints carry the
+                          penalty beta * w_e, and the residual-balancing rule of section 3.4, on link e's
+                          own residuals and the same cadence, moves w_e by C within [w_min, w_max],
+                          dividing link e's scaled duals by the same factor).  Graph engine with CSC link
+                          sums; not with record.  Default 0 */
+  double w_min, w_max; /* bounds on w_e; default 0.25 and 4 */
 } te_options;
 
 typedef struct {
@@ -186,6 +208,16 @@ te_status te_solve(te_ctx *ctx, const te_options *opt, void *hip_stream, const f
 te_status te_project(te_ctx *ctx, void *hip_stream, float *x_out_dev, float *S_out_dev);
 
 /*
+ * The FP64 iterate the handle's last graph-engine solve left, before any projection: its path rates
+ * x_r and per-demand sums S_c = sum of the rates of c, in caller units.  This is what that solve's
+ * projection started from, and the exact state a later warm = 1 solve continues from.
+ *   x_out_dev [n_paths] double, S_out_dev nullable [n_demands] double,
+ *   w_out_dev nullable [n_links] double: per-link penalty factors w_e (all 1 unless per_link)
+ * TE_ERR_STATE as te_project.
+ */
+te_status te_get_state(te_ctx *ctx, void *hip_stream, double *x_out_dev, double *S_out_dev, double *w_out_dev);
+
+/*
  * Algorithm 2 (section 3.5) applied to caller-supplied path rates under the handle's CURRENT
  * capacities and demands (those of te_create or the last te_update), with the trim order of the
  * given alpha.  This is how an allocation computed for an earlier network state is scored under a
@@ -243,9 +275,25 @@ void te_destroy(te_ctx *ctx);
 void te_destroy_batch(te_batch *batch);
 
 /* Sizes of a handle: n_links, n_paths, n_demands, nnz, max paths per demand, engine AUTO would pick,
- * workgroups of the graph engine's demand kernel and of its link kernel, and the 16-bit slots per
- * path of the demand kernel's hop records (0: it reads the CSR path layout instead). */
-te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [9] */);
+ * workgroups of the graph engine's demand kernel and of its link kernel, the 16-bit slots per
+ * path of the demand kernel's hop records (0: it reads the CSR path layout instead), the
+ * generation of the recording te_grad would use (0: none; every recorded solve and every
+ * te_update changes it, and te_update discards the recording), the graph engine's link sums in use
+ * (TE_LINK_SUMS_PRIVATE or TE_LINK_SUMS_CSC) and its privatised-sum workgroups (0 with CSC sums).
+ * The demand and link workgroups are those of the link sums in use. */
+te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [12] */);
+
+/*
+ * Per-iteration trace of the handle's last te_solve, when it ran with opt->trace = 1 or
+ * opt->record = 1: the control sequence of Algorithm 1 with the residual balancing of section 3.4.
+ *   hip_stream the stream that solve ran on (synchronised here)
+ *   cap        rows of out; out is a host array [4][cap]: out[k] = beta_k, out[cap + k] = alpha_k
+ *              (penalty and fairness used in iteration k), out[2 cap + k] = r_k, out[3 cap + k] = s_k
+ *              (dual and primal residual of iteration k, normalised units)
+ *   n_out      iterations written: min(iterations run, cap)
+ * TE_ERR_STATE if that solve ran without a trace, or te_grad / te_kernel_times ran since.
+ */
+te_status te_trace(te_ctx *ctx, void *hip_stream, int32_t cap, double *out, int32_t *n_out);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
 const char *te_last_error(void);

@@ -46,13 +46,14 @@ class _Options(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("adapt_beta", ctypes.c_int32), ("project", ctypes.c_int32),
                 ("collapsed", ctypes.c_int32), ("sched_beta", ctypes.c_void_p), ("sched_alpha", ctypes.c_void_p),
                 ("sched_len", ctypes.c_int32), ("root_max_steps", ctypes.c_int32),
-                ("dual_res_scaled", ctypes.c_int32), ("beta_every", ctypes.c_int32), ("warm", ctypes.c_void_p)]
+                ("dual_res_scaled", ctypes.c_int32), ("beta_every", ctypes.c_int32), ("warm", ctypes.c_void_p),
+                ("per_link", ctypes.c_int32), ("w_min", ctypes.c_double), ("w_max", ctypes.c_double)]
 
 
 class _Warm(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("S", ctypes.c_void_p), ("y", ctypes.c_void_p), ("ucon", ctypes.c_void_p),
                 ("ucap", ctypes.c_void_p), ("udem", ctypes.c_void_p), ("uneg", ctypes.c_void_p),
-                ("beta", ctypes.c_double), ("alpha", ctypes.c_double)]
+                ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("w", ctypes.c_void_p)]
 
 
 class _Stats(ctypes.Structure):
@@ -67,7 +68,7 @@ class _State(ctypes.Structure):
     _fields_ = [("dual_dem", ctypes.c_void_p), ("dual_cap", ctypes.c_void_p), ("dual_neg", ctypes.c_void_p),
                 ("dual_con", ctypes.c_void_p), ("y", ctypes.c_void_p), ("x_raw", ctypes.c_void_p),
                 ("S_raw", ctypes.c_void_p), ("trace", ctypes.c_void_p), ("trace_cap", ctypes.c_int32),
-                ("scale", ctypes.c_double)]
+                ("scale", ctypes.c_double), ("w", ctypes.c_void_p)]
 
 
 def _load():
@@ -87,6 +88,8 @@ def _load():
         lib.gate_oracle_grad.restype = ctypes.c_int
         lib.gate_oracle_grad.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P, P, ctypes.c_double,
                                          ctypes.c_int, P, P, P, P, P, P]
+        lib.gate_oracle_threads.restype = ctypes.c_int
+        lib.gate_oracle_threads.argtypes = [ctypes.c_int]
         lib.gate_oracle_project.restype = ctypes.c_int
         lib.gate_oracle_project.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, ctypes.c_int, P, P,
                                             ctypes.c_double, P, P, P]
@@ -114,6 +117,9 @@ class Options:
     root_max_steps: int = 200
     dual_res_scaled: bool = False
     beta_every: int = 5
+    per_link: bool = False   # per-link penalties beta * w_e, w_e adapted per link
+    w_min: float = 0.25      # bounds on w_e (wider bounds let the rule starve a link's penalty: with
+    w_max: float = 4.0       # [1e-2, 1e2] a 7-node instance stalled at alpha = 0)
 
 
 @dataclass
@@ -141,6 +147,7 @@ class Result:
     dual_neg: np.ndarray
     dual_con: np.ndarray
     y: np.ndarray
+    w: np.ndarray            # [E] per-link penalty factors at the end (ones without per_link)
 
     @property
     def schedule(self):
@@ -154,7 +161,7 @@ class Result:
         s = self.scale
         return dict(x=self.x_raw * s, S=self.S_raw * s, y=self.y * s, ucon=self.dual_con * s,
                     ucap=self.dual_cap * s, udem=self.dual_dem * s, uneg=self.dual_neg * s,
-                    beta=self.beta, alpha=self.final_alpha)
+                    beta=self.beta, alpha=self.final_alpha, w=self.w.copy())
 
 
 def _p(a):
@@ -189,6 +196,9 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
     o.root_max_steps = opts.root_max_steps
     o.dual_res_scaled = int(opts.dual_res_scaled)
     o.beta_every = int(opts.beta_every)
+    o.per_link = int(opts.per_link)
+    o.w_min = float(opts.w_min)
+    o.w_max = float(opts.w_max)
     sb = sa = None
     if opts.sched_beta is not None:
         sb = np.ascontiguousarray(opts.sched_beta, np.float64)
@@ -207,6 +217,8 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
     st.S_raw = S_raw.ctypes.data
     st.trace = trace.ctypes.data
     st.trace_cap = trace.shape[0]
+    w_out = np.ones(E)
+    st.w = w_out.ctypes.data
     dd = dc = dn = dcon = yy = None
     if want_state:
         dd, dc, dn, dcon, yy = np.zeros(D), np.zeros(E), np.zeros(P), np.zeros(max(nnz, 1)), np.zeros(max(nnz, 1))
@@ -224,6 +236,12 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
             setattr(w, name, a.ctypes.data)
         w.beta = float(warm["beta"])
         w.alpha = float(warm["alpha"])
+        if warm.get("w") is not None:
+            wa = np.ascontiguousarray(warm["w"], np.float64)
+            if wa.shape != (E,):
+                raise ValueError(f"warm['w'] has shape {wa.shape}, expected ({E},)")
+            wkeep.append(wa)
+            w.w = wa.ctypes.data
         wkeep.append(w)
         o.warm = ctypes.addressof(w)
     stats = _Stats()
@@ -238,14 +256,21 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
                   max_cap_viol_rel=stats.max_cap_viol_rel, max_dem_viol_rel=stats.max_dem_viol_rel,
                   collapse_dev=stats.collapse_dev, root_steps_mean=stats.root_steps_mean,
                   root_steps_max=stats.root_steps_max, trace=trace[:it].copy(), dual_dem=dd, dual_cap=dc,
-                  dual_neg=dn, dual_con=None if dcon is None else dcon[:nnz], y=None if yy is None else yy[:nnz])
+                  dual_neg=dn, dual_con=None if dcon is None else dcon[:nnz], y=None if yy is None else yy[:nnz],
+                  w=w_out)
+
+
+def threads(n: int = 0) -> int:
+    """Set the oracle's OpenMP threads for later calls (n > 0); returns the threads in use."""
+    return int(_load().gate_oracle_threads(int(n)))
 
 
 def sum_root(a, n_links, uneg, D, udem, alpha, beta, S0):
-    """Root S of one commodity's sum equation and the rates x_r (appendix B.2)."""
+    """Root S of one commodity's sum equation and the rates x_r (appendix B.2).  n_links: links per
+    path, or with per-link penalties the weights W_r = sum of the factors w_e of the path's links."""
     lib = _load()
     a = np.ascontiguousarray(a, np.float64)
-    n = np.ascontiguousarray(n_links, np.int32)
+    n = np.ascontiguousarray(n_links, np.float64)
     u = np.ascontiguousarray(uneg, np.float64)
     x = np.zeros(a.shape[0])
     S = ctypes.c_double(0.0)

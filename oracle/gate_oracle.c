@@ -51,6 +51,22 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP loops for later calls (n > 0), or just the current setting (n <= 0);
+   returns the number the next parallel loop may use (1 when built without OpenMP).  Timing aid of
+   the CPU baseline only: the arithmetic does not depend on it. */
+int gate_oracle_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 #define GO_CONVERGED 1
 #define GO_HIT_MAX_ITERS 2
@@ -73,6 +89,8 @@ typedef struct {
   const double *uneg;  /* [P] */
   double beta;         /* penalty the duals are scaled for */
   double alpha;        /* fairness reached (capped at alpha_target) */
+  const double *w;     /* nullable [E]: per-link penalty factors (per_link); the link duals are scaled
+                          for beta * w_e */
 } go_warm;
 
 typedef struct {
@@ -94,6 +112,8 @@ typedef struct {
   int32_t dual_res_scaled;   /* 1: s = beta * ||x^{k+1} - x^k||, 0: as printed, without beta */
   int32_t beta_every;        /* apply the residual-balancing rule after every T-th sweep (READING) */
   const go_warm *warm;       /* nullable: continue from this state instead of initialising */
+  int32_t per_link;          /* 1: per-link penalties beta * w_e, w_e adapted per link (READING) */
+  double w_min, w_max;       /* bounds on w_e */
 } go_options;
 
 typedef struct {
@@ -117,6 +137,7 @@ typedef struct {
   double *trace;    /* [5 * n] rows (alpha, beta, r, s, flags-so-far) per sweep */
   int32_t trace_cap;
   double scale;     /* out: normalisation scale s */
+  double *w;        /* [E] per-link penalty factors at the end (all 1 without per_link) */
 } go_state;
 
 /* ------------------------------------------------------------------------ */
@@ -137,7 +158,7 @@ typedef struct {
 typedef struct {
   int np;
   const double *a;
-  const int *n;        /* links per path */
+  const double *n;     /* links per path: n_r, or with per-link penalties W_r = sum_{e in r} w_e */
   const double *uneg;  /* dual_neg per path */
   double D, udem, alpha, beta;
 } commodity_t;
@@ -160,11 +181,11 @@ static double dh_of(const commodity_t *c, double S) {
   return d;
 }
 
-static double xi(double b, int n, double uneg) {
+static double xi(double b, double n, double uneg) {
   return (b >= n * uneg) ? b / n : (b + uneg) / (n + 1);
 }
 
-static double dxi(double b, int n, double uneg) {
+static double dxi(double b, double n, double uneg) {
   return (b >= n * uneg) ? 1.0 / n : 1.0 / (n + 1);
 }
 
@@ -257,10 +278,11 @@ static double sum_root(const commodity_t *c, double S0, int max_steps, int *step
 }
 
 /* Exported for pins: solve one commodity's sum equation and the rates. */
-int gate_oracle_sum_root(int np, const double *a, const int32_t *n_links, const double *uneg,
+int gate_oracle_sum_root(int np, const double *a, const double *n_links, const double *uneg,
                          double D, double udem, double alpha, double beta, double S0,
                          double *S_out, double *x_out) {
-  int *n = (int *)malloc(sizeof(int) * (size_t)np);
+  /* n_links: n_r, or the weights W_r of per-link penalties */
+  double *n = (double *)malloc(sizeof(double) * (size_t)np);
   for (int r = 0; r < np; ++r) n[r] = n_links[r];
   commodity_t c = {np, a, n, uneg, D, udem, alpha, beta};
   int steps;
@@ -419,6 +441,12 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   /* incidence bookkeeping: n_r, link -> incidences (CSR positions), n_e */
   int *n_r = (int *)malloc(sizeof(int) * (size_t)P);
   for (int r = 0; r < P; ++r) n_r[r] = (int)(path_ptr[r + 1] - path_ptr[r]);
+  /* per-link penalty factors w_e (READING, per-link penalties): link e's consensus and capacity
+     constraints carry the penalty beta * w_e, the demand and non-negativity constraints beta; the
+     x-block weighs link e's terms by w_e, so n_r becomes W_r = sum_{e in r} w_e */
+  double *w = (double *)malloc(sizeof(double) * (size_t)(E ? E : 1));
+  double *W_r = (double *)malloc(sizeof(double) * (size_t)(P ? P : 1));
+  for (int e = 0; e < E; ++e) w[e] = (opt->warm && opt->warm->w) ? opt->warm->w[e] : 1.0;
   int32_t *lptr = (int32_t *)calloc((size_t)E + 1, sizeof(int32_t));
   for (int64_t i = 0; i < nnz; ++i) lptr[path_links[i] + 1]++;
   for (int e = 0; e < E; ++e) lptr[e + 1] += lptr[e];
@@ -509,6 +537,11 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
       beta = opt->sched_beta[kk];
     }
     memcpy(x_prev, x, sizeof(double) * (size_t)P);
+    for (int r = 0; r < P; ++r) {
+      double t = 0.0;
+      for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) t += w[path_links[i]];
+      W_r[r] = opt->per_link ? t : (double)n_r[r];
+    }
 
     /* 1. x-block: per commodity, exact minimisation via the sum equation */
 #pragma omp parallel for schedule(dynamic, 64) if (D > 1024)
@@ -517,22 +550,26 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
       for (int r = r0; r < r0 + m; ++r) {
         double s = 0.0;
         if (opt->collapsed) {
-          /* a_r = n_r x_r - sum_{e in r} (g_e - q_e) (equal to the line below after sweep 1) */
-          for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) s += gq_q[path_links[i]] - gq_g[path_links[i]];
-          s += n_r[r] * x[r];
+          /* a_r = W_r x_r - sum_{e in r} w_e (g_e - q_e) (equal to the line below after sweep 1) */
+          for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) {
+            const int e = path_links[i];
+            s += opt->per_link ? w[e] * (gq_q[e] - gq_g[e]) : gq_q[e] - gq_g[e];
+          }
+          s += W_r[r] * x[r];
         } else {
-          for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) s += y[i] - ucon[i];
+          for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i)
+            s += opt->per_link ? w[path_links[i]] * (y[i] - ucon[i]) : y[i] - ucon[i];
         }
         a[r] = s;
       }
-      commodity_t cm = {m, a + r0, n_r + r0, uneg + r0, Dm[c], udem[c], alpha, beta};
+      commodity_t cm = {m, a + r0, W_r + r0, uneg + r0, Dm[c], udem[c], alpha, beta};
       int steps;
       double Sst = sum_root(&cm, S[c], max_steps, &steps);
       steps_c[c] = steps;
       double h = h_of(&cm, Sst);
       double sum = 0.0;
       for (int r = r0; r < r0 + m; ++r) {
-        x[r] = xi(a[r] - h, n_r[r], uneg[r]);
+        x[r] = xi(a[r] - h, W_r[r], uneg[r]);
         sum += x[r];
       }
       S[c] = sum;
@@ -639,6 +676,30 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
       for (int r = 0; r < P; ++r) uneg[r] /= f;
       for (int64_t i = 0; i < nnz; ++i) ucon[i] /= f;
     }
+    /* 5b. per-link penalties (READING): the same residual-balancing rule, on the same cadence, per
+       link e on its own residuals -- r_e = the change of link e's scaled duals (its capacity dual
+       and the consensus duals of its paths; each equals that constraint's residual), s_e = the
+       change of the rates of the paths through e -- moves w_e by C within [w_min, w_max] and divides
+       link e's scaled duals by the same factor */
+    if (opt->per_link && ((k + 1) % (opt->beta_every > 0 ? opt->beta_every : 1)) == 0) {
+      for (int e = 0; e < E; ++e) {
+        if (lptr[e + 1] == lptr[e]) continue;
+        double s2 = 0.0;
+        for (int jj = lptr[e]; jj < lptr[e + 1]; ++jj) s2 += ds[lpaths[jj]];
+        const double re = sqrt(de[e]), se = sqrt(s2);
+        double fe = 1.0;
+        if (re > opt->A * se) {
+          if (w[e] * opt->C <= opt->w_max) fe = opt->C;
+        } else if (se > opt->A * re) {
+          if (w[e] / opt->C >= opt->w_min) fe = 1.0 / opt->C;
+        }
+        if (fe == 1.0) continue;
+        w[e] *= fe;
+        ucap[e] /= fe;
+        gq_g[e] /= fe;
+        for (int jj = lptr[e]; jj < lptr[e + 1]; ++jj) ucon[linc[jj]] /= fe;
+      }
+    }
 
     /* 6. alpha-increments and stop (Algorithm 1).  READING: a stop needs
      * alpha >= 1 and convergence on the first sweep after an increment;
@@ -690,6 +751,7 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
 
   if (st) {
     st->scale = scale;
+    if (st->w) memcpy(st->w, w, sizeof(double) * (size_t)E);
     if (st->x_raw) for (int r = 0; r < P; ++r) st->x_raw[r] = x[r];
     if (st->S_raw) for (int c = 0; c < D; ++c) st->S_raw[c] = S[c];
     if (st->dual_dem) memcpy(st->dual_dem, udem, sizeof(double) * (size_t)D);
@@ -718,7 +780,7 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
       S_out[c] = s * scale;
     }
 
-  free(C); free(Dm); free(n_r); free(lptr); free(fill); free(linc); free(lpaths); free(inc_path);
+  free(C); free(Dm); free(n_r); free(w); free(W_r); free(lptr); free(fill); free(linc); free(lpaths); free(inc_path);
   free(x); free(x_prev); free(y); free(ucon); free(ucap); free(udem); free(uneg); free(S); free(a);
   free(gq_g); free(gq_q); free(dr); free(ds); free(dd); free(de); free(steps_c);
   return 0;
@@ -762,6 +824,8 @@ int gate_oracle_grad(int n_links, const double *capacity, int n_paths, const int
   int *n_r = (int *)malloc(sizeof(int) * (size_t)P);
   int *dem_of = (int *)malloc(sizeof(int) * (size_t)P);
   for (int r = 0; r < P; ++r) n_r[r] = (int)(path_ptr[r + 1] - path_ptr[r]);
+  double *n_rd = (double *)malloc(sizeof(double) * (size_t)(P ? P : 1)); /* n_r as the x-block takes it */
+  for (int r = 0; r < P; ++r) n_rd[r] = n_r[r];
   for (int c = 0; c < D; ++c) for (int r = demand_path_ptr[c]; r < demand_path_ptr[c + 1]; ++r) dem_of[r] = c;
   int32_t *lptr = (int32_t *)calloc((size_t)E + 1, sizeof(int32_t));
   for (int64_t i = 0; i < nnz; ++i) lptr[path_links[i] + 1]++;
@@ -808,7 +872,7 @@ int gate_oracle_grad(int n_links, const double *capacity, int n_paths, const int
         for (int64_t i = path_ptr[r]; i < path_ptr[r + 1]; ++i) acc += y[i] - ucon[i];
         a[r] = acc;
       }
-      commodity_t cm = {m, a + r0, n_r + r0, uneg + r0, Dm[c], udem[c], alpha, beta};
+      commodity_t cm = {m, a + r0, n_rd + r0, uneg + r0, Dm[c], udem[c], alpha, beta};
       int steps;
       double Sst = sum_root(&cm, Sws[c], 200, &steps);
       double h = h_of(&cm, Sst), sum = 0.0;
@@ -1005,6 +1069,6 @@ int gate_oracle_grad(int n_links, const double *capacity, int n_paths, const int
   free(sw); free(y); free(ucon); free(ucap); free(udem); free(uneg); free(Sws); free(a);
   free(bx); free(by); free(bucon); free(bucap); free(budem); free(buneg); free(bC); free(bD);
   free(nby); free(nucon); free(nucap); free(nudem); free(nuneg); free(bS); free(ba);
-  free(C); free(Dm); free(n_r); free(dem_of); free(lptr); free(fill); free(linc); free(inc_path);
+  free(C); free(Dm); free(n_r); free(n_rd); free(dem_of); free(lptr); free(fill); free(linc); free(inc_path);
   return 0;
 }

@@ -19,10 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libte_gate.so")
 TE_OK, TE_ERR_INVALID, TE_ERR_OOM, TE_ERR_DEVICE, TE_ERR_NUMERIC, TE_ERR_STATE = range(6)
 TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
 ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
+LINK_SUMS_AUTO, LINK_SUMS_PRIVATE, LINK_SUMS_CSC = 0, 1, 2
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
-       "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_destroy", "te_destroy_batch", "te_info",
-       "te_last_error"]
+       "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_get_state", "te_trace", "te_destroy", "te_destroy_batch",
+       "te_info", "te_last_error"]
 
 
 class TEError(RuntimeError):
@@ -39,7 +40,9 @@ class _Options(ctypes.Structure):
                 ("project", ctypes.c_int32), ("engine", ctypes.c_int32), ("record", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("paths_per_lane", ctypes.c_int32), ("warm", ctypes.c_int32), ("sched_beta", ctypes.c_void_p),
-                ("sched_alpha", ctypes.c_void_p), ("sched_len", ctypes.c_int32)]
+                ("sched_alpha", ctypes.c_void_p), ("sched_len", ctypes.c_int32), ("trace", ctypes.c_int32),
+                ("link_sums", ctypes.c_int32), ("per_link", ctypes.c_int32), ("w_min", ctypes.c_double),
+                ("w_max", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -88,6 +91,10 @@ def library(path: str = LIB_PATH):
     lib.te_project.argtypes = [P, P, P, P]
     lib.te_project_rates.restype = I
     lib.te_project_rates.argtypes = [P, P, P, ctypes.c_double, P, P]
+    lib.te_get_state.restype = I
+    lib.te_get_state.argtypes = [P, P, P, P, P]
+    lib.te_trace.restype = I
+    lib.te_trace.argtypes = [P, P, I, P, ctypes.POINTER(I)]
     lib.te_kernel_times.restype = I
     lib.te_kernel_times.argtypes = [P, ctypes.POINTER(_Options), P, I, P]
     lib.te_destroy.restype = None
@@ -128,6 +135,11 @@ class Options:
     block_threads: int = 0             # workgroup engine: 256, 512, 1024; 0 = default / tuned for batches
     paths_per_lane: int = 0            # workgroup engine: 1, 2, 4, 8; 0 = default / tuned for batches
     warm: bool = False                 # continue from the handle's last graph-engine state
+    trace: bool = False                # log (beta_k, alpha_k, r_k, s_k) per iteration (Problem.trace)
+    link_sums: int = LINK_SUMS_AUTO    # graph engine: privatised (LDS rows) or CSC segmented link sums
+    per_link: bool = False             # per-link adaptive penalties beta * w_e (graph engine, CSC sums)
+    w_min: float = 0.25
+    w_max: float = 4.0
     sched_beta: np.ndarray | None = None
     sched_alpha: np.ndarray | None = None
 
@@ -153,6 +165,11 @@ class Options:
         o.block_threads = self.block_threads
         o.paths_per_lane = self.paths_per_lane
         o.warm = int(self.warm)
+        o.trace = int(self.trace)
+        o.link_sums = int(self.link_sums)
+        o.per_link = int(self.per_link)
+        o.w_min = float(self.w_min)
+        o.w_max = float(self.w_max)
         keep = []
         if self.sched_beta is not None:
             sb = np.ascontiguousarray(self.sched_beta, np.float64)
@@ -200,11 +217,12 @@ class Problem:
         self.n_links, self.n_paths, self.n_demands = cap.shape[0], pptr.shape[0] - 1, dem.shape[0]
 
     def info(self):
-        sz = np.zeros(9, np.int64)
+        sz = np.zeros(12, np.int64)
         _check(library().te_info(self._h, sz.ctypes.data))
         return dict(n_links=int(sz[0]), n_paths=int(sz[1]), n_demands=int(sz[2]), nnz=int(sz[3]),
                     max_paths=int(sz[4]), auto_engine=int(sz[5]), demand_workgroups=int(sz[6]),
-                    link_workgroups=int(sz[7]), hop_slots=int(sz[8]))
+                    link_workgroups=int(sz[7]), hop_slots=int(sz[8]), record_gen=int(sz[9]),
+                    link_sums=int(sz[10]), scatter_workgroups=int(sz[11]))
 
     def update(self, capacity=None, demand=None):
         c = None if capacity is None else np.ascontiguousarray(capacity, np.float64)
@@ -245,6 +263,16 @@ class Problem:
         _check(library().te_grad(self._h, sp, dS.data_ptr(), dC.data_ptr(), dD.data_ptr()))
         return dC, dD
 
+    def trace(self, cap: int, stream=None):
+        """Per-iteration trace of the last solve run with trace=True or record=True (te_trace):
+        returns a float64 array [n, 4] of (beta_k, alpha_k, r_k, s_k)."""
+        import torch
+        out = np.zeros((4, max(int(cap), 0)), np.float64)
+        n = ctypes.c_int32(0)
+        sp = _stream_ptr(torch.device("cuda", self.device)) if stream is None else stream
+        _check(library().te_trace(self._h, sp, int(cap), out.ctypes.data, ctypes.byref(n)))
+        return out[:, :n.value].T.copy()
+
     def project(self, x_out=None, S_out=None, stream=None):
         """Feasible allocation (Algorithm 2) from the state the last graph-engine solve left (te_project):
         returns (x [n_paths], S [n_demands]) float32 cuda tensors in caller units."""
@@ -257,6 +285,19 @@ class Problem:
         sp = _stream_ptr(dev) if stream is None else stream
         _check(library().te_project(self._h, sp, x_out.data_ptr(), S_out.data_ptr()))
         return x_out, S_out
+
+    def state(self, stream=None, with_w=False):
+        """The FP64 rates and per-demand sums the last graph-engine solve left, before projection
+        (te_get_state): returns (x [n_paths], S [n_demands]) float64 cuda tensors in caller units, and
+        with with_w=True also the per-link penalty factors w [n_links]."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        x = torch.empty(self.n_paths, dtype=torch.float64, device=dev)
+        S = torch.empty(self.n_demands, dtype=torch.float64, device=dev)
+        w = torch.empty(self.n_links, dtype=torch.float64, device=dev) if with_w else None
+        sp = _stream_ptr(dev) if stream is None else stream
+        _check(library().te_get_state(self._h, sp, x.data_ptr(), S.data_ptr(), None if w is None else w.data_ptr()))
+        return (x, S, w) if with_w else (x, S)
 
     def project_rates(self, x, alpha, x_out=None, S_out=None, stream=None):
         """Algorithm 2 applied to the given path rates x (caller units) under the handle's current
@@ -364,10 +405,14 @@ def _autograd_function():
             problem.update(C.detach().cpu().numpy(), D.detach().cpu().numpy())
             _, S, _ = problem.solve(o, stats=False)
             ctx.problem = problem
+            ctx.gen = problem.info()["record_gen"]
             return S.clone()
 
         @staticmethod
         def backward(ctx, gS):
+            if ctx.problem.info()["record_gen"] != ctx.gen:
+                raise RuntimeError("GateSolve: the problem was solved again (or updated) after this forward; "
+                                   "its recording no longer describes this output")
             dC, dD = ctx.problem.grad(gS)
             return None, dC.cpu(), dD.cpu(), None, None
 

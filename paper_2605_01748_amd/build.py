@@ -7,9 +7,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libte_gate.so")
 SOURCES = [os.path.join(HERE, "csrc", "te_kernels.hip"), os.path.join(HERE, "csrc", "te_runtime.cpp")]
-# measurement of kernel boundaries against grid barriers (bench.py --probe-sync)
-PROBE_LIB = os.path.join(HERE, "libte_probe.so")
-PROBE_SOURCES = [os.path.join(HERE, "csrc", "sync_probe.hip")]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-result"]
@@ -31,7 +28,6 @@ def _hipcc(sources, out, verbose):
 
 def build(verbose: bool = False) -> str:
     _hipcc(SOURCES, LIB, verbose)
-    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

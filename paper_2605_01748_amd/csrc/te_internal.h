@@ -32,6 +32,8 @@ struct Params {
   int32_t kmax;        // iteration cap
   int32_t fixed;       // 1: fixed iteration count, no stop
   int32_t adapt_beta, beta_every, alpha_max;
+  int32_t per_link;    // 1: link e's constraints carry beta * w_e, w_e moved by the per-link rule
+  double w_min, w_max; // bounds on w_e
   int32_t sched_len;
   const double *sched_beta;   // device, nullable
   const double *sched_alpha;  // device, nullable
@@ -65,7 +67,16 @@ struct Prob {
   // demand kernel of the graph engine: paths per lane (1 = one lane per path) and log2 of its
   // lanes per demand, max(1, G / ppl)
   int32_t ppl, logGp;
+  // how the link loads are summed: kLinkSumsPrivate (each demand workgroup sums its paths' rates
+  // into an LDS copy of the E loads, one row per workgroup, rows reduced per link) or kLinkSumsCsc
+  // (segmented sums over the link -> path CSC list)
+  int32_t lsum;
+  // privatised sums: passes of kScatThreads / 2^logGp demands, spw consecutive passes per scatter
+  // workgroup, nF workgroups (rows of partial loads)
+  int32_t npass, spw, nF;
 };
+
+enum { kLinkSumsPrivate = 1, kLinkSumsCsc = 2 };
 
 constexpr int kMaxHopSlots = 16;
 // graph engine: instances with at least kMultiLanes lane slots (demands x G) run the demand step
@@ -76,19 +87,22 @@ constexpr int kMultiPaths = 2;
 // Iteration state on the device.
 struct State {
   double *x, *uneg;  // [P] path rates and non-negativity duals
-  float *xf;         // [P] FP32 copy of x, read by the link kernel's gathers (half the bytes)
   double *udem, *S;  // [D] demand duals and last root of the sum equation
   double2 *gq;       // [E] (g, q): g = capacity / consensus dual, q = consensus offset
+  double *w;         // [E] per-link penalty factors (1 without per-link penalties)
+  double *dx2;       // [P] (x' - x)^2 of the iteration, written where the per-link rule needs it
   // where an iteration writes its new x, u_neg, u_dem, S and (g, q): the arrays above (in place),
   // or another state block (the gradient's recomputation writes iteration k + 1 next to k)
   double *xo, *unego, *udemo, *So;
   double2 *gqo;
   Ctrl *ctrl;        // [3]
-  double *partA;     // [2][nA * waves per workgroup][4]: the demand kernels' per-wavefront rows
-  double *partB;     // [2][nB][4]
-  int32_t nA, nB;
-  double *log_beta;  // nullable [log_cap]: (beta_k, alpha_k) actually used, written when recording
-  double *log_alpha;
+  double *partA;     // [2][nArows][4]: the demand kernels' per-wavefront rows (nA workgroups)
+  double *partB;     // [2][nB][4]: the link kernel's per-workgroup rows
+  int32_t nA, nB, nArows;
+  double *partL;     // [nF][E] privatised sums: each scatter workgroup's share of the link loads
+  // nullable [4][log_cap]: per iteration k the beta_k and alpha_k it used and its residuals r_k, s_k
+  // (rows beta | alpha | r | s), written when recording for the gradient or tracing
+  double *log;
   int32_t log_cap;
 };
 
@@ -115,6 +129,10 @@ constexpr int kThreads = 256;        // threads per workgroup of the graph-engin
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kLinkWaves = kLinkThreads / 64;
 constexpr int kBlockThreads = 1024;  // threads of the workgroup engine for single solves
+constexpr int kScatThreads = 1024;   // threads per workgroup of the privatised-sum demand kernel
+// privatised sums: the scatter workgroup's LDS copy of the loads (8 bytes a link) and the link
+// reduction's workgroups (64 links each, at most kMaxLinkBlocks) bound the links
+constexpr int kMaxScatterLinks = 19456;
 constexpr int kBlockPathsPerLane = 4;  // paths per lane of the workgroup engine for single solves
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
@@ -144,6 +162,8 @@ struct Pools {
   const double *Dn;    // [sum D]
   const double *Cn;    // [sum E]
   const float *x0;     // nullable [sum P] warm start, caller units
+  double *log;         // nullable [4][log_cap] per-iteration log of workgroup 0's instance (as State::log)
+  int32_t log_cap;
 };
 
 struct BatchOut {

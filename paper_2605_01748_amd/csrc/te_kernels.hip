@@ -85,6 +85,25 @@ __device__ __forceinline__ void wave_partials(double a, double b, double d, doub
   }
 }
 
+// The link kernel's workgroup 0 publishes this iteration's control record (pending: its decision
+// is taken by the next iteration's kernels) and logs it when a log is attached: iteration k's beta
+// and alpha, and the residuals of iteration k - 1 that the decision was taken from.
+__device__ __forceinline__ void publish_ctrl(const State &s, const Ctrl &cs, int par) {
+  Ctrl wr = cs;
+  wr.pending = cs.stop ? 0 : 1;
+  s.ctrl[par] = wr;
+  if (s.log) {
+    if (!cs.stop && cs.k < s.log_cap) {
+      s.log[cs.k] = cs.beta;
+      s.log[s.log_cap + cs.k] = cs.alpha;
+    }
+    if (cs.k >= 1 && cs.k <= s.log_cap) {
+      s.log[2 * s.log_cap + cs.k - 1] = cs.r;
+      s.log[3 * s.log_cap + cs.k - 1] = cs.s;
+    }
+  }
+}
+
 // XCD-aware work order.  The dispatcher deals the workgroups of a launch round-robin over the 8
 // XCDs (workgroup b runs on XCD b % 8, each XCD with its own L2).  Processing logical block
 // xcd_chunk(b) instead of b gives every XCD one contiguous range of the logical work: the demand
@@ -139,14 +158,16 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, dou
     for (int r = r0; r < r1; ++r) {
       const double v = x0 ? (double)x0[r] * inv_scale : p.Dn[c] / (double)(r1 - r0);
       s.x[r] = v;
-      s.xf[r] = (float)v;
       s.uneg[r] = 0.0;
       sum += v;
     }
     s.udem[c] = 0.0;
     s.S[c] = sum;
   }
-  for (int e = tid; e < p.E; e += nth) s.gq[e] = make_double2(0.0, 0.0);
+  for (int e = tid; e < p.E; e += nth) {
+    s.gq[e] = make_double2(0.0, 0.0);
+    s.w[e] = 1.0;
+  }
   if (tid == 0) {
     Ctrl c = initial_ctrl(prm);
     s.ctrl[1] = c;   // read as "iteration -1" by iteration 0, not pending
@@ -158,15 +179,16 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, dou
 // Continuation from the state of the previous solve (warm restart): rate-like state converted to
 // the current units (rescale = old scale / new scale), the control record restarted at iteration 0
 // with the previous beta and alpha (alpha capped at the target; a replayed schedule overrides both).
+// The scaled duals in memory are still at the penalty of the last iteration run (the rescale that
+// the final decision took is applied lazily by the next iteration), so the first iteration divides
+// them by beta_new / beta_last, like any other change of beta.
 __global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
   const Params &prm = *prmp;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   if (rescale != 1.0) {
     for (int r = tid; r < p.P; r += nth) {
-      const double v = s.x[r] * rescale;
-      s.x[r] = v;
-      s.xf[r] = (float)v;
+      s.x[r] *= rescale;
       s.uneg[r] *= rescale;
     }
     for (int c = tid; c < p.D; c += nth) {
@@ -185,6 +207,7 @@ __global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
       c.beta = fin.beta;
       c.alpha = fmin(fin.alpha, prm.alpha_target);
     }
+    c.inv_f = fin.beta * fin.inv_f / c.beta;  // penalty of the stored duals over the new one
     s.ctrl[0] = c;
     s.ctrl[1] = c;
     s.ctrl[2] = c;
@@ -237,6 +260,35 @@ __device__ __forceinline__ void gather_path(const Prob &p, const State &s, int r
   }
 }
 
+// The same with per-link penalty factors: sums of w_e g_e and w_e q_e over path r's links, and
+// W_r = sum of w_e (the path's weight in the rate update, n_r when every w_e is 1).
+__device__ __forceinline__ void gather_path_w(const Prob &p, const State &s, int r, double &sg, double &sq,
+                                              double &Wr) {
+  sg = 0.0;
+  sq = 0.0;
+  Wr = 0.0;
+  const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
+  for (int ib = i0; ib < i1; ib += 8) {
+    int e[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (e[u] >= 0) {
+        const double2 v = s.gq[e[u]];
+        const double we = s.w[e[u]];
+        sg += we * v.x;
+        sq += we * v.y;
+        Wr += we;
+      }
+  }
+}
+
+// the per-link rule acts after this iteration (the same cadence as the residual-balancing rule)
+__device__ __forceinline__ bool per_link_rule_now(const Params &prm, const Ctrl &cs) {
+  return prm.per_link && ((cs.k + 1) % prm.beta_every) == 0;
+}
+
 __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
@@ -252,7 +304,7 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
   const int c = bl * (kThreads >> p.logG) + (t >> p.logG);
   // gathers (independent of the control record): sums of g and q along the path
   int r0 = 0, np = 0, r = 0, n = 1;
-  double xr = 0.0, ung = 0.0, Dc = 0.0;
+  double xr = 0.0, ung = 0.0, Dc = 0.0, Wn = 1.0;
   double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
   bool on = false;
   if (!ctl && c < p.D) {
@@ -266,7 +318,12 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
     if (on) {
       xr = s.x[r];
       ung = s.uneg[r];
-      gather_path(p, s, r, sg, sq, n);
+      if (prm.per_link) {
+        gather_path_w(p, s, r, sg, sq, Wn);
+      } else {
+        gather_path(p, s, r, sg, sq, n);
+        Wn = (double)n;
+      }
     }
   }
   if (ctl) finish_ctrl(cp, prm, &cs);
@@ -277,11 +334,11 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
   if (c < p.D) {
     Lane L;
     L.on = on;
-    L.a = on ? (double)n * xr - (sg * inv_f - sq) : 0.0;
+    L.a = on ? Wn * xr - (sg * inv_f - sq) : 0.0;
     L.un = ung * inv_f;
-    L.n = (double)n;
-    L.rn = 1.0 / (double)n;
-    L.rn1 = 1.0 / (double)(n + 1);
+    L.n = Wn;
+    L.rn = 1.0 / Wn;
+    L.rn1 = 1.0 / (Wn + 1.0);
     Dem dm;
     dm.D = Dc;
     dm.u = udc * inv_f;
@@ -295,10 +352,10 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
     if (L.on) {
       const double un = fmax(L.un - xn, 0.0);
       s.xo[r] = xn;
-      s.xf[r] = (float)xn;
       s.unego[r] = un;
       ds2 = (xn - xr) * (xn - xr);
       dr2 = (un - L.un) * (un - L.un);
+      if (per_link_rule_now(prm, cs)) s.dx2[r] = ds2;
     }
     if (lane == 0) {
       const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
@@ -328,13 +385,12 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
   const int c = bl * (kThreads >> logGp) + (t >> logGp);
   int r0 = 0, np = 0;
   double Dc = 0.0, udc = 0.0, S0 = 0.0;
-  double xr[PPL], ung[PPL], sg[PPL], sq[PPL];
-  int n[PPL];
+  double xr[PPL], ung[PPL], sg[PPL], sq[PPL], Wn[PPL];
   unsigned on = 0u;
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     xr[j] = ung[j] = sg[j] = sq[j] = 0.0;
-    n[j] = 1;
+    Wn[j] = 1.0;
   }
   if (c < p.D) {
     Dc = p.Dn[c];
@@ -350,7 +406,13 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
         on |= 1u << j;
         xr[j] = s.x[r];
         ung[j] = s.uneg[r];
-        gather_path(p, s, r, sg[j], sq[j], n[j]);
+        if (prm.per_link) {
+          gather_path_w(p, s, r, sg[j], sq[j], Wn[j]);
+        } else {
+          int nj;
+          gather_path(p, s, r, sg[j], sq[j], nj);
+          Wn[j] = (double)nj;
+        }
       }
     }
   }
@@ -365,11 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       const bool oj = (on >> j) & 1u;
-      L.a[j] = oj ? (double)n[j] * xr[j] - (sg[j] * inv_f - sq[j]) : 0.0;
+      L.a[j] = oj ? Wn[j] * xr[j] - (sg[j] * inv_f - sq[j]) : 0.0;
       L.un[j] = ung[j] * inv_f;
-      L.n[j] = (double)n[j];
-      L.rn[j] = 1.0 / (double)n[j];
-      L.rn1[j] = 1.0 / (double)(n[j] + 1);
+      L.n[j] = Wn[j];
+      L.rn[j] = 1.0 / Wn[j];
+      L.rn1[j] = 1.0 / (Wn[j] + 1.0);
     }
     Dem dm;
     dm.D = Dc;
@@ -379,6 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
     int steps;
     const double Sst = sum_root(S0, L, dm, Gp, &steps);
     const double h = h_of(Sst, dm);
+    const bool rule = per_link_rule_now(prm, cs);
     double xsum = 0.0;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
@@ -388,8 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
       const double xn = (b >= L.n[j] * L.un[j]) ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
       const double un = fmax(L.un[j] - xn, 0.0);
       s.xo[r] = xn;
-      s.xf[r] = (float)xn;
       s.unego[r] = un;
+      if (rule) s.dx2[r] = (xn - xr[j]) * (xn - xr[j]);
       xsum += xn;
       ds2 += (xn - xr[j]) * (xn - xr[j]);
       dr2 += (un - L.un[j]) * (un - L.un[j]);
@@ -482,10 +545,31 @@ __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0
 // link inside the row with a segmented scan and adds one partial per run into an LDS FP64
 // accumulator.  Also folds a slice of the demand kernel's partial sums into its row.
 // ------------------------------------------------------------------------------------------
+// Per-link penalties: the residual-balancing rule on link e's own residuals r_e (the change of its
+// scaled duals, sqrt((1 + n_e)) |g' - g|) and s_e (the change of the rates of its paths,
+// sqrt(sum_{r on e} (x'_r - x_r)^2)) moves w_e by C within [w_min, w_max]; the new g is divided by
+// the same factor (q is a rate offset and keeps its value).  Returns the g to store.
+__device__ __forceinline__ double per_link_rule(const Params &prm, double *w, int e, int ne, double gold,
+                                                double gn, double sx2) {
+  const double re = sqrt((double)(1 + ne) * ((gn - gold) * (gn - gold)));
+  const double se = sqrt(sx2);
+  const double we = w[e];
+  double fe = 1.0;
+  if (re > prm.A * se) {
+    if (we * prm.C <= prm.w_max) fe = prm.C;
+  } else if (se > prm.A * re) {
+    if (we / prm.C >= prm.w_min) fe = 1.0 / prm.C;
+  }
+  if (fe == 1.0) return gn;
+  w[e] = we * fe;
+  return gn / fe;
+}
+
 __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Params *prmp, int par) {
   const Params &prm = *prmp;
   __shared__ Ctrl cs;
   __shared__ double acc[kMaxLinksPerBlock];
+  __shared__ double acc2[kMaxLinksPerBlock];  // per-link rule: sum of (x' - x)^2 over the link's paths
   __shared__ double fold[3];
   CtrlPrefetch cp;
   if (threadIdx.x < 64) prefetch_ctrl(s, par, cp);
@@ -508,8 +592,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
   }
   double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
   if (w == 1) {  // fold the demand kernel's per-wavefront rows b, b + nB, ... (fixed order)
-    const double *pa = s.partA + (size_t)par * s.nA * (kThreads / 64) * 4;
-    for (int i = bl + lane * gridDim.x; i < s.nA * (kThreads / 64); i += 64 * gridDim.x) {
+    const double *pa = s.partA + (size_t)par * s.nArows * 4;
+    for (int i = bl + lane * gridDim.x; i < s.nArows; i += 64 * gridDim.x) {
       a0 += pa[4 * i + 0];
       a1 += pa[4 * i + 1];
       a3 = fmax(a3, pa[4 * i + 3]);
@@ -524,19 +608,18 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     }
   }
   __syncthreads();
-  seg_rows_sum(p.lpf, s.xf, k0, wt, acc);
+  seg_rows_sum(p.lpf, (const double *)s.xo, k0, wt, acc);
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    Ctrl wr = cs;
-    wr.pending = cs.stop ? 0 : 1;
-    s.ctrl[par] = wr;
-    if (s.log_beta && !cs.stop && cs.k < s.log_cap) {
-      s.log_beta[cs.k] = cs.beta;
-      s.log_alpha[cs.k] = cs.alpha;
-    }
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) publish_ctrl(s, cs, par);
   if (cs.stop) return;
+  const bool rule = per_link_rule_now(prm, cs);  // uniform in the workgroup
+  if (rule) {
+    for (int k = threadIdx.x; k < k1 - k0; k += blockDim.x) acc2[k] = 0.0;
+    __syncthreads();
+    seg_rows_sum(p.lpf, (const double *)s.dx2, k0, wt, acc2);
+    __syncthreads();
+  }
   const double inv_f = cs.inv_f;
   double dr2 = 0.0, cap_v = -INFINITY;
   if (k1 - k0 <= 64) {
@@ -547,7 +630,8 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
       const double load = acc[kf - k0];
       const double gold = gq_f.x * inv_f;
       const double gn = fmax(gold + (load - C_f) / (double)(1 + ne_f), 0.0);
-      s.gqo[e_f] = make_double2(gn, gold - gn);
+      const double gs = rule ? per_link_rule(prm, s.w, e_f, ne_f, gold, gn, acc2[kf - k0]) : gn;
+      s.gqo[e_f] = make_double2(gs, gold - gn);
       dr2 = (double)(1 + ne_f) * (gn - gold) * (gn - gold);
       cap_v = (load - C_f) / C_f;
     }
@@ -575,13 +659,299 @@ __global__ __launch_bounds__(kLinkThreads) void k_link(Prob p, State s, const Pa
     const double load = acc[k - k0];
     const double gold = v.x * inv_f;
     const double gn = fmax(gold + (load - Ce) / (double)(1 + ne), 0.0);
-    s.gqo[e] = make_double2(gn, gold - gn);
+    const double gs = rule ? per_link_rule(prm, s.w, e, ne, gold, gn, acc2[k - k0]) : gn;
+    s.gqo[e] = make_double2(gs, gold - gn);
     dr2 += (double)(1 + ne) * (gn - gold) * (gn - gold);
     cap_v = fmax(cap_v, (load - Ce) / Ce);
   }
   const bool t0 = threadIdx.x == 0;
   block_partials(t0 ? fold[0] : 0.0, dr2 + (t0 ? fold[1] : 0.0), cap_v, t0 ? fold[2] : -INFINITY,
                  s.partB + ((size_t)par * s.nB + bl) * 4);
+}
+
+// ------------------------------------------------------------------------------------------
+// Privatised link sums (instances with at most kMaxScatterLinks links).  One iteration =
+//   k_demand_scatter: steps a1 + a2 as in the demand kernels above, and step a3 inside the
+//                     workgroup: every path's new rate is added into the workgroup's own LDS copy of
+//                     the E link loads (FP64 atomics in LDS, on the link ids already in registers
+//                     from the gather), written out once as the workgroup's row of partial loads;
+//   k_link_reduce:    per link, the sum of those rows in workgroup order, then step a4.
+// Neither reads the link -> path list nor gathers a rate a second time.  A scatter workgroup runs
+// spw passes over consecutive demands (kScatThreads / 2^logGp demands a pass), so there are few
+// rows: one per workgroup.
+// ------------------------------------------------------------------------------------------
+
+// Link ids of one path as the gather read them, kept in registers for the scatter: the words of its
+// hop record (H > 0), or its CSR range.
+struct PathIds {
+  uint2 w[kMaxHopSlots / 4];
+  int i0, i1;
+};
+
+__device__ __forceinline__ void gather_ids(const Prob &p, const State &s, int r, PathIds &id, double &sg,
+                                           double &sq, int &n) {
+  sg = 0.0;
+  sq = 0.0;
+  if (p.H > 0) {
+    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) id.w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+    n = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      const unsigned e4[4] = {id.w[q].x & 0xffffu, id.w[q].x >> 16, id.w[q].y & 0xffffu, id.w[q].y >> 16};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e4[u] != 0xffffu) {
+          const double2 v = s.gq[e4[u]];
+          sg += v.x;
+          sq += v.y;
+          ++n;
+        }
+    }
+  } else {
+    id.i0 = p.pptr[r];
+    id.i1 = p.pptr[r + 1];
+    n = id.i1 - id.i0;
+    for (int ib = id.i0; ib < id.i1; ib += 8) {
+      int e8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e8[u] = ib + u < id.i1 ? p.plinks[ib + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e8[u] >= 0) {
+          const double2 v = s.gq[e8[u]];
+          sg += v.x;
+          sq += v.y;
+        }
+    }
+  }
+}
+
+// acc[e] += v for every link e of path r, its link ids read again (from the caches: the gather
+// read them in the same pass)
+__device__ __forceinline__ void scatter_path(const Prob &p, int r, double v, double *acc) {
+  if (p.H > 0) {
+    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      if (4 * q >= p.H) break;
+      const uint2 wq = rec[q];
+      const unsigned e4[4] = {wq.x & 0xffffu, wq.x >> 16, wq.y & 0xffffu, wq.y >> 16};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e4[u] != 0xffffu) atomicAdd(&acc[e4[u]], v);
+    }
+  } else {
+    for (int i = p.pptr[r]; i < p.pptr[r + 1]; ++i) atomicAdd(&acc[p.plinks[i]], v);
+  }
+}
+
+// acc[e] += v for every link e of the path
+__device__ __forceinline__ void scatter_ids(const Prob &p, const PathIds &id, double v, double *acc) {
+  if (p.H > 0) {
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      const unsigned e4[4] = {id.w[q].x & 0xffffu, id.w[q].x >> 16, id.w[q].y & 0xffffu, id.w[q].y >> 16};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e4[u] != 0xffffu) atomicAdd(&acc[e4[u]], v);
+    }
+  } else {
+    for (int i = id.i0; i < id.i1; ++i) atomicAdd(&acc[p.plinks[i]], v);
+  }
+}
+
+// KEEP: the gather's link ids stay in registers for the scatter (one path per lane), or are read
+// again (several paths per lane, where keeping them would spill)
+template <int PPL>
+__global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s, const Params *prmp, int par) {
+  constexpr bool KEEP = PPL == 1;
+  const Params &prm = *prmp;
+  extern __shared__ double acc[];  // [E]: this workgroup's share of every link load
+  __shared__ Ctrl cs;
+  CtrlPrefetch cp;
+  const int t = threadIdx.x;
+  if (t < 64) prefetch_ctrl(s, par, cp);
+  for (int e = t; e < p.E; e += kScatThreads) acc[e] = 0.0;
+  const int logGp = p.logGp, Gp = 1 << logGp;
+  const int lane = t & (Gp - 1);
+  const int per = kScatThreads >> logGp;
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int ps0 = bl * p.spw, ps1 = min(ps0 + p.spw, p.npass);
+  double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
+  for (int ps = ps0; ps < ps1; ++ps) {  // bounds uniform in the workgroup
+    const int c = ps * per + (t >> logGp);
+    int r0 = 0, np = 0;
+    double Dc = 0.0, udc = 0.0, S0 = 0.0;
+    double xr[PPL], ung[PPL], sg[PPL], sq[PPL];
+    int n[PPL];
+    PathIds ids[KEEP ? PPL : 1];
+    unsigned on = 0u;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+      xr[j] = ung[j] = sg[j] = sq[j] = 0.0;
+      n[j] = 1;
+    }
+    if (c < p.D) {
+      Dc = p.Dn[c];
+      udc = s.udem[c];
+      S0 = s.S[c];
+      r0 = p.dptr[c];
+      np = p.dptr[c + 1] - r0;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        const int idx = lane + j * Gp;
+        if (idx < np) {
+          const int r = r0 + idx;
+          on |= 1u << j;
+          xr[j] = s.x[r];
+          ung[j] = s.uneg[r];
+          if (KEEP)
+            gather_ids(p, s, r, ids[0], sg[j], sq[j], n[j]);
+          else
+            gather_path(p, s, r, sg[j], sq[j], n[j]);
+        }
+      }
+    }
+    if (ps == ps0) {
+      if (t < 64) finish_ctrl(cp, prm, &cs);
+      __syncthreads();  // the decision, and the zeroed accumulators
+      if (cs.stop) return;
+    }
+    if (c < p.D) {
+      const double inv_f = cs.inv_f;
+      LaneN<PPL> L;
+      L.on = on;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        const bool oj = (on >> j) & 1u;
+        L.a[j] = oj ? (double)n[j] * xr[j] - (sg[j] * inv_f - sq[j]) : 0.0;
+        L.un[j] = ung[j] * inv_f;
+        L.n[j] = (double)n[j];
+        L.rn[j] = 1.0 / (double)n[j];
+        L.rn1[j] = 1.0 / (double)(n[j] + 1);
+      }
+      Dem dm;
+      dm.D = Dc;
+      dm.u = udc * inv_f;
+      dm.alpha = cs.alpha;
+      dm.binv = 1.0 / cs.beta;
+      int steps;
+      const double Sst = sum_root(S0, L, dm, Gp, &steps);
+      const double h = h_of(Sst, dm);
+      double xsum = 0.0;
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+        if (!((on >> j) & 1u)) continue;
+        const int r = r0 + lane + j * Gp;
+        const double b = L.a[j] - h;
+        const double xn = (b >= L.n[j] * L.un[j]) ? b * L.rn[j] : (b + L.un[j]) * L.rn1[j];
+        const double un = fmax(L.un[j] - xn, 0.0);
+        s.xo[r] = xn;
+        s.unego[r] = un;
+        if (KEEP)
+          scatter_ids(p, ids[0], xn, acc);
+        else
+          scatter_path(p, r, xn, acc);
+        xsum += xn;
+        ds2 += (xn - xr[j]) * (xn - xr[j]);
+        dr2 += (un - L.un[j]) * (un - L.un[j]);
+      }
+      const double Ssum = group_sum_d(xsum, Gp);
+      if (lane == 0) {
+        const double ud = fmax(dm.u + Ssum - dm.D, 0.0);
+        s.udemo[c] = ud;
+        s.So[c] = Sst;
+        dr2 += (ud - dm.u) * (ud - dm.u);
+        dem_v = fmax(dem_v, (Ssum - dm.D) / dm.D);
+      }
+    }
+  }
+  wave_partials(ds2, dr2, dem_v, s.partA + ((size_t)par * s.nA + bl) * (kScatThreads / 64) * 4);
+  __syncthreads();  // every LDS addition done
+  double *row = s.partL + (size_t)bl * p.E;
+  for (int e = t; e < p.E; e += kScatThreads) row[e] = acc[e];
+}
+
+// Step a3 across workgroups + step a4: workgroup b owns links 64 b .. 64 b + 63; wavefront w sums
+// rows w, w + 16, ... of the partial loads (eight loads in flight), the per-wavefront sums are added
+// in wavefront order, and the first wavefront updates the links' duals and writes the workgroup's
+// row of partial sums.  Also folds a slice of the scatter kernel's per-wavefront rows into that row.
+__global__ __launch_bounds__(kLinkThreads) void k_link_reduce(Prob p, State s, const Params *prmp, int par) {
+  const Params &prm = *prmp;
+  __shared__ Ctrl cs;
+  __shared__ double red[kLinkWaves][64];
+  __shared__ double fold[3];
+  CtrlPrefetch cp;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  if (t < 64) prefetch_ctrl(s, par, cp);
+  const int bl = xcd_chunk(blockIdx.x, gridDim.x);
+  const int e = bl * 64 + lane;
+  const bool in = e < p.E;
+  int ne = 0;
+  double2 gq_f = make_double2(0.0, 0.0);
+  double C_f = 1.0;
+  if (w == 0 && in) {
+    ne = p.lptr[e + 1] - p.lptr[e];
+    gq_f = s.gq[e];
+    C_f = p.Cn[e];
+  }
+  if (w == 1) {  // fold the scatter kernel's per-wavefront rows b, b + nB, ... (fixed order)
+    double a0 = 0.0, a1 = 0.0, a3 = -INFINITY;
+    const double *pa = s.partA + (size_t)par * s.nArows * 4;
+    for (int i = bl + lane * gridDim.x; i < s.nArows; i += 64 * gridDim.x) {
+      a0 += pa[4 * i + 0];
+      a1 += pa[4 * i + 1];
+      a3 = fmax(a3, pa[4 * i + 3]);
+    }
+    a0 = wave_sum_d(a0);
+    a1 = wave_sum_d(a1);
+    a3 = wave_max_d(a3);
+    if (lane == 0) {
+      fold[0] = a0;
+      fold[1] = a1;
+      fold[2] = a3;
+    }
+  }
+  double a = 0.0;
+  if (in) {
+    const double *col = s.partL + e;
+    int r = w;
+    for (; r + 7 * kLinkWaves < p.nF; r += 8 * kLinkWaves) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(r + u * kLinkWaves) * p.E];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a += v[u];
+    }
+    for (; r < p.nF; r += kLinkWaves) a += col[(size_t)r * p.E];
+  }
+  red[w][lane] = a;
+  if (t < 64) finish_ctrl(cp, prm, &cs);
+  __syncthreads();
+  if (blockIdx.x == 0 && t == 0) publish_ctrl(s, cs, par);
+  if (cs.stop || w != 0) return;
+  double load = 0.0;
+#pragma unroll
+  for (int i = 0; i < kLinkWaves; ++i) load += red[i][lane];
+  double dr2 = 0.0, cap_v = -INFINITY;
+  if (in && ne > 0) {
+    const double gold = gq_f.x * cs.inv_f;
+    const double gn = fmax(gold + (load - C_f) / (double)(1 + ne), 0.0);
+    s.gqo[e] = make_double2(gn, gold - gn);
+    dr2 = (double)(1 + ne) * (gn - gold) * (gn - gold);
+    cap_v = (load - C_f) / C_f;
+  }
+  dr2 = wave_sum_d(dr2);
+  cap_v = wave_max_d(cap_v);
+  if (lane == 0) {
+    double *o = s.partB + ((size_t)par * s.nB + bl) * 4;
+    o[0] = fold[0];
+    o[1] = dr2 + fold[1];
+    o[2] = cap_v;
+    o[3] = fold[2];
+  }
 }
 
 // Final control record: applies the decision pending after the last iteration.
@@ -603,7 +973,14 @@ __global__ void k_finish(State s, const Params *prmp, int last_par) {
       v[2] = wave_max_d(v[2]);
       v[3] = wave_max_d(v[3]);
     }
-    if (threadIdx.x == 0) s.ctrl[2] = decide(prev, v, prm);
+    if (threadIdx.x == 0) {
+      const Ctrl fin = decide(prev, v, prm);
+      s.ctrl[2] = fin;
+      if (s.log && fin.k >= 1 && fin.k <= s.log_cap) {  // residuals of the last iteration
+        s.log[2 * s.log_cap + fin.k - 1] = fin.r;
+        s.log[3 * s.log_cap + fin.k - 1] = fin.s;
+      }
+    }
   }
 }
 
@@ -856,26 +1233,50 @@ __global__ __launch_bounds__(256) void kp_link_trim(Prob p, ProjBuf b) {
   }
 }
 
-// step 6 and outputs in caller units (rounded toward zero: the FP32 rates stay feasible)
+// step 6 and outputs in caller units.  Projected rates are rounded toward zero (the FP32 rates stay
+// feasible) and S is the sum of the returned rates; unprojected rates are rounded to nearest and S
+// is their FP64 sum rounded once (the rates of a demand may have either sign before the projection,
+// so a sum of rounded rates could lose the small sums to cancellation).
 __global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double scale, int project, const double *xs) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
     double sum = 0.0;
     for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
-      double v;
       if (project) {
-        v = b.xd[r] - __longlong_as_double((long long)b.trim[r]);
+        double v = b.xd[r] - __longlong_as_double((long long)b.trim[r]);
         v = fmax(v, 0.0) * scale;
         x_out[r] = __double2float_rz(v);
+        sum += (double)x_out[r];
       } else {
-        v = xs[r] * scale;
-        x_out[r] = (float)v;
+        x_out[r] = (float)(xs[r] * scale);
+        sum += xs[r];
       }
-      sum += (double)x_out[r];
     }
-    if (S_out) S_out[c] = (float)sum;
+    if (S_out) S_out[c] = project ? (float)sum : (float)(sum * scale);
   }
+}
+
+// the FP64 rates (and sums) of the state, caller units
+__global__ void k_get_state(Prob p, State s, double scale, double *x_out, double *S_out) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nth = gridDim.x * blockDim.x;
+  for (int c = tid; c < p.D; c += nth) {
+    double sum = 0.0;
+    for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
+      x_out[r] = s.x[r] * scale;
+      sum += s.x[r];
+    }
+    if (S_out) S_out[c] = sum * scale;
+  }
+}
+
+hipError_t launch_get_state(const Prob &p, const State &s, double scale, double *x_out, double *S_out,
+                            hipStream_t st) {
+  int blocks = (p.D + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(k_get_state, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, st, p, s, scale, x_out, S_out);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1076,7 +1477,15 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
       }
       Ctrl c = cs;
       c.pending = 1;
-      cs = decide(c, v, prm);
+      const Ctrl nc = decide(c, v, prm);
+      if (pools.log && blockIdx.x == 0 && c.k < pools.log_cap) {  // this iteration's beta, alpha, r, s
+        const int L = pools.log_cap;
+        pools.log[c.k] = c.beta;
+        pools.log[L + c.k] = c.alpha;
+        pools.log[2 * L + c.k] = nc.r;
+        pools.log[3 * L + c.k] = nc.s;
+      }
+      cs = nc;
     }
     __syncthreads();
   }
@@ -1156,9 +1565,9 @@ __global__ __launch_bounds__(NT) void k_block_solve(const BatchDesc *descs, Pool
       if (project) v = fmax(v - (double)xo[r], 0.0);
       const float o = project ? __double2float_rz(v * scale) : (float)(v * scale);
       xo[r] = o;
-      sum += (double)o;
+      sum += project ? (double)o : v;  // unprojected: the FP64 sum, rounded once (as kp_output)
     }
-    if (S_out) S_out[d.off_D + c] = (float)sum;
+    if (S_out) S_out[d.off_D + c] = project ? (float)sum : (float)(sum * scale);
   }
   if (tid == 0) {
     BatchOut o;
@@ -1369,8 +1778,27 @@ static void launch_demand_k(K kern, int threads, const Prob &p, const State &s, 
     hipLaunchKernelGGL(kern, dim3(s.nA), dim3(threads), 0, st, p, s, prm, par);
 }
 
+template <class K>
+static void launch_scatter_k(K kern, const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                             hipEvent_t ev0, hipEvent_t ev1) {
+  const size_t lds = sizeof(double) * (size_t)p.E;
+  if (ev0)
+    hipExtLaunchKernelGGL(kern, dim3(p.nF), dim3(kScatThreads), lds, st, ev0, ev1, 0, p, s, prm, par);
+  else
+    hipLaunchKernelGGL(kern, dim3(p.nF), dim3(kScatThreads), lds, st, p, s, prm, par);
+}
+
 static void launch_demand_kernel(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
                                  hipEvent_t ev0, hipEvent_t ev1) {
+  if (p.lsum == kLinkSumsPrivate) {
+    switch (p.ppl) {
+      case 2: launch_scatter_k(k_demand_scatter<2>, p, s, prm, par, st, ev0, ev1); break;
+      case 4: launch_scatter_k(k_demand_scatter<4>, p, s, prm, par, st, ev0, ev1); break;
+      case 8: launch_scatter_k(k_demand_scatter<8>, p, s, prm, par, st, ev0, ev1); break;
+      default: launch_scatter_k(k_demand_scatter<1>, p, s, prm, par, st, ev0, ev1);
+    }
+    return;
+  }
   switch (p.ppl) {
     case 2: launch_demand_k(k_demand_multi<2>, kThreads, p, s, prm, par, st, ev0, ev1); break;
     case 4: launch_demand_k(k_demand_multi<4>, kThreads, p, s, prm, par, st, ev0, ev1); break;
@@ -1379,9 +1807,36 @@ static void launch_demand_kernel(const Prob &p, const State &s, const Params *pr
   }
 }
 
+static void launch_link_kernel(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
+                               hipEvent_t ev0, hipEvent_t ev1) {
+  if (p.lsum == kLinkSumsPrivate) {
+    if (ev0)
+      hipExtLaunchKernelGGL(k_link_reduce, dim3(s.nB), dim3(kLinkThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
+    else
+      hipLaunchKernelGGL(k_link_reduce, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
+  } else if (ev0) {
+    hipExtLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
+  } else {
+    hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
+  }
+}
+
+// dynamic LDS of the privatised-sum demand kernels up to kMaxScatterLinks links (above the default
+// limit of a launch); once per process and device before their first launch
+hipError_t prepare_scatter_kernels() {
+  const int lds = (int)(sizeof(double) * kMaxScatterLinks);
+  const void *ks[] = {(const void *)k_demand_scatter<1>, (const void *)k_demand_scatter<2>,
+                      (const void *)k_demand_scatter<4>, (const void *)k_demand_scatter<8>};
+  for (const void *k : ks) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_iteration(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st) {
   launch_demand_kernel(p, s, prm, par, st, nullptr, nullptr);
-  hipLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, p, s, prm, par);
+  launch_link_kernel(p, s, prm, par, st, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1393,7 +1848,7 @@ hipError_t launch_demand_timed(const Prob &p, const State &s, const Params *prm,
 
 hipError_t launch_link_timed(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1) {
-  hipExtLaunchKernelGGL(k_link, dim3(s.nB), dim3(kLinkThreads), 0, st, ev0, ev1, 0, p, s, prm, par);
+  launch_link_kernel(p, s, prm, par, st, ev0, ev1);
   return hipGetLastError();
 }
 

@@ -36,6 +36,8 @@ hipError_t launch_adj_seed(const Prob &, const AdjState &, const float *, hipStr
 hipError_t launch_adj_iteration(const Prob &, int, const FwdState &, const FwdState &, const AdjState &, double,
                                 double, double, hipStream_t);
 hipError_t launch_adj_x0(const Prob &, const AdjState &, hipStream_t);
+hipError_t prepare_scatter_kernels();
+hipError_t launch_get_state(const Prob &, const State &, double, double *, double *, hipStream_t);
 }  // namespace te
 
 using namespace te;
@@ -89,6 +91,9 @@ hipError_t dalloc(T **p, size_t n) {
 struct te_ctx {
   int device = 0;
   int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0, ppl = 1, logGp = 0;
+  int32_t lsum = kLinkSumsCsc;  // link sums of the graph engine in use (Prob::lsum)
+  int32_t nB_csc = 0;           // workgroups of the CSC link kernel (also the adjoint's link kernel)
+  int32_t ncu = 256;            // compute units of the device
   double scale = 1.0;
   // host layout (kept for batches and updates)
   std::vector<int32_t> pptr, plinks, dptr, lptr, lpaths;
@@ -118,15 +123,24 @@ struct te_ctx {
   hipGraphExec_t chunk = nullptr;
   hipGraphExec_t rec_chunk = nullptr;
   double *rec_chunk_log = nullptr;
+  // the same with the per-iteration trace (te_options.trace) into d_trace
+  hipGraphExec_t trace_chunk = nullptr;
+  double *trace_chunk_log = nullptr;
   int32_t *h_flag = nullptr;  // pinned: stop flags of chunks in flight
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing
   hipEvent_t pe[2] = {nullptr, nullptr};    // polling of the stop flag
   size_t lds_bytes = 0;
   // recorded solve for te_grad
   int32_t rec_K = 0, rec_ck = 16, rec_warm = 0;
+  int64_t rec_gen = 0;  // bumped by every completed recording and every te_update
   double state_scale = 0.0;  // unit scale of the state the last graph-engine solve left (0: none)
-  double *d_log = nullptr;      // [2 * log_cap]: beta log then alpha log
+  double *d_log = nullptr;      // [4 * log_cap]: beta, alpha, r, s of the recorded iterations
   int32_t log_cap = 0;
+  double *d_trace = nullptr;    // [4 * trace_cap]: the same for a solve run with trace = 1
+  int32_t trace_cap = 0;
+  int32_t trace_engine = 0;     // engine of the last traced solve (0: none since the last untraced one)
+  double *trace_src = nullptr;  // d_log or d_trace: where the last traced solve wrote
+  int32_t trace_src_cap = 0;
   std::vector<FwdState> ckpt;   // checkpoints every rec_ck iterations
   std::vector<Ctrl *> ckpt_ctrl;
   std::vector<FwdState> seg;    // one segment of recomputed states
@@ -183,6 +197,11 @@ void te_default_options(te_options *o) {
   o->sched_beta = nullptr;
   o->sched_alpha = nullptr;
   o->sched_len = 0;
+  o->trace = 0;
+  o->link_sums = TE_LINK_SUMS_AUTO;
+  o->per_link = 0;
+  o->w_min = 0.25;
+  o->w_max = 4.0;
 }
 
 te_status te_validate(int32_t n_links, const double *capacity, int32_t n_paths, const int64_t *path_ptr,
@@ -281,6 +300,9 @@ te_status stage_params(Params **d_params, Params *h_params, hipEvent_t ev, doubl
   p.adapt_beta = o->adapt_beta;
   p.beta_every = o->beta_every > 0 ? o->beta_every : 1;
   p.alpha_max = o->alpha_max;
+  p.per_link = o->per_link;
+  p.w_min = o->w_min;
+  p.w_max = o->w_max;
   p.sched_len = 0;
   p.sched_beta = p.sched_alpha = nullptr;
   if (o->sched_beta && o->sched_alpha && o->sched_len > 0) {
@@ -314,6 +336,15 @@ te_status check_options(const te_options *o) {
   if (o->paths_per_lane != 0 && o->paths_per_lane != 1 && o->paths_per_lane != 2 && o->paths_per_lane != 4 &&
       o->paths_per_lane != 8)
     return fail(TE_ERR_INVALID, "paths_per_lane must be 0, 1, 2, 4 or 8");
+  if (o->link_sums < 0 || o->link_sums > 2) return fail(TE_ERR_INVALID, "link_sums must be 0, 1 or 2");
+  if (o->per_link) {
+    if (!(o->w_min > 0.0) || !(o->w_max >= o->w_min) || !(1.0 >= o->w_min) || !(1.0 <= o->w_max))
+      return fail(TE_ERR_INVALID, "per_link needs 0 < w_min <= 1 <= w_max");
+    if (o->link_sums == TE_LINK_SUMS_PRIVATE)
+      return fail(TE_ERR_INVALID, "per_link runs with the CSC link sums (link_sums 0 or 2)");
+    if (o->record) return fail(TE_ERR_INVALID, "per_link cannot be recorded for te_grad");
+    if (o->engine == TE_ENGINE_BLOCK) return fail(TE_ERR_INVALID, "per_link runs on the graph engine");
+  }
   return TE_OK;
 }
 
@@ -342,6 +373,20 @@ te_status capture_chunk(te_ctx *c, const State &st, hipGraphExec_t *out) {
 
 te_status build_chunk_graph(te_ctx *c, hipStream_t) { return capture_chunk(c, c->st, &c->chunk); }
 
+// The iteration chunk that also writes the per-iteration trace into st.log (recaptured when the
+// trace buffer has moved).
+te_status trace_graph(te_ctx *c, const State &st, hipGraphExec_t *out) {
+  if (c->trace_chunk && c->trace_chunk_log != st.log) {
+    HIPCHK(hipGraphExecDestroy(c->trace_chunk));
+    c->trace_chunk = nullptr;
+  }
+  te_status s = capture_chunk(c, st, &c->trace_chunk);
+  if (s != TE_OK) return s;
+  c->trace_chunk_log = st.log;
+  *out = c->trace_chunk;
+  return TE_OK;
+}
+
 // Paths per lane of the graph engine's demand kernel: one lane per path, or -- for instances with
 // at least kMultiLanes lane slots (demands x G), where that kernel is bound by issue and bandwidth
 // rather than latency -- min(G, kMultiPaths).
@@ -349,27 +394,70 @@ int default_graph_ppl(const te_ctx *c) {
   return (int64_t)c->D * c->G >= kMultiLanes ? std::min(c->G, kMultiPaths) : 1;
 }
 
-void set_graph_ppl(te_ctx *c, int ppl) {
+// Rows of per-wavefront partial sums the demand kernels can leave: one lane per path with the CSC
+// link kernel (the largest grid), or 16 per scatter workgroup.
+int64_t partA_rows(const te_ctx *c) {
+  const int64_t csc = (int64_t)((c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG)) * (kThreads / 64);
+  const int64_t scat = (int64_t)c->ncu * (kScatThreads / 64);
+  return std::max(csc, scat);
+}
+
+// Launch shape of the graph engine for ppl paths per lane and link sums lsum (kLinkSums*).
+// Privatised sums: passes of kScatThreads / 2^logGp demands, dealt in runs of spw consecutive
+// passes to at most one scatter workgroup per compute unit (each holds the E loads in LDS).
+void set_graph_shape(te_ctx *c, int ppl, int lsum) {
   int logp = 0;
   while ((1 << logp) < ppl) ++logp;
   c->ppl = ppl;
   c->logGp = c->logG > logp ? c->logG - logp : 0;
-  c->st.nA = (c->D + (kThreads >> c->logGp) - 1) / (kThreads >> c->logGp);
-  c->prob.ppl = c->ppl;
-  c->prob.logGp = c->logGp;
+  c->lsum = lsum;
+  Prob &p = c->prob;
+  p.ppl = c->ppl;
+  p.logGp = c->logGp;
+  p.lsum = lsum;
+  if (lsum == kLinkSumsPrivate) {
+    const int per = kScatThreads >> c->logGp;
+    p.npass = (c->D + per - 1) / per;
+    p.spw = (p.npass + c->ncu - 1) / c->ncu;
+    p.nF = (p.npass + p.spw - 1) / p.spw;
+    c->st.nA = p.nF;
+    c->st.nArows = p.nF * (kScatThreads / 64);
+    c->st.nB = (c->E + 63) / 64;
+  } else {
+    p.npass = p.spw = p.nF = 0;
+    c->st.nA = (c->D + (kThreads >> c->logGp) - 1) / (kThreads >> c->logGp);
+    c->st.nArows = c->st.nA * (kThreads / 64);
+    c->st.nB = c->nB_csc;
+  }
 }
 
-// The option's paths per lane (0: the default) for the graph engine; a change recaptures the
-// iteration graphs, which hold the demand kernel's launch shape.
-te_status select_graph_ppl(te_ctx *c, const te_options &o) {
+// Link sums of the graph engine by default: privatised for instances with at least kMultiLanes lane
+// slots (demands x G) whose links fit one workgroup's LDS -- there the kernels are bound by bandwidth
+// and issue, and the privatised sums save the second pass over the incidence (measured on the
+// 1,000-node instance) -- else CSC: smaller instances are latency-bound, and the scatter kernel's one
+// pass of 1,024-thread workgroups plus the row reduction cost more than the CSC link kernel
+// (measured on the 150-node instance).
+int default_link_sums(const te_ctx *c) {
+  return ((int64_t)c->D * c->G >= kMultiLanes && c->E <= kMaxScatterLinks) ? kLinkSumsPrivate : kLinkSumsCsc;
+}
+
+// The options' paths per lane (0: the default) and link sums (0: default_link_sums) for the graph
+// engine; a change recaptures the iteration graphs, which hold the kernels' launch shapes.
+te_status select_graph_shape(te_ctx *c, const te_options &o) {
   const int want = o.paths_per_lane ? o.paths_per_lane : default_graph_ppl(c);
-  if (want == c->ppl) return TE_OK;
+  int lsum = o.link_sums ? o.link_sums : default_link_sums(c);
+  if (o.per_link) lsum = kLinkSumsCsc;  // the per-link rule needs per-link sums of (x' - x)^2
+  if (lsum == kLinkSumsPrivate && c->E > kMaxScatterLinks)
+    return fail(TE_ERR_INVALID, "privatised link sums hold at most %d links (instance: %d)", kMaxScatterLinks, c->E);
+  if (want == c->ppl && lsum == c->lsum) return TE_OK;
   HIPCHK(hipDeviceSynchronize());  // no launch of the old graphs may still be in flight
   if (c->chunk) HIPCHK(hipGraphExecDestroy(c->chunk));
   if (c->rec_chunk) HIPCHK(hipGraphExecDestroy(c->rec_chunk));
+  if (c->trace_chunk) HIPCHK(hipGraphExecDestroy(c->trace_chunk));
   c->chunk = nullptr;
   c->rec_chunk = nullptr;
-  set_graph_ppl(c, want);
+  c->trace_chunk = nullptr;
+  set_graph_shape(c, want, lsum);
   return TE_OK;
 }
 
@@ -544,14 +632,22 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   // index pool: pptr | plinks | dptr | lptr | lpaths
   const size_t ni = (size_t)(c->P + 1) + c->nnz + (c->D + 1) + (c->E + 1) + c->nnz + c->nnz + c->nzlink.size() +
                     c->nzptr.size() + c->blk.size();
-  // demand kernel mapping (partials are allocated for one lane per path, the largest grid)
-  set_graph_ppl(c, default_graph_ppl(c));
-  const int nA1 = (c->D + (kThreads >> c->logG) - 1) / (kThreads >> c->logG);
+  // launch shapes: CSC link kernel of nB workgroups, or the privatised sums when the links fit
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+      c->ncu = prop.multiProcessorCount;
+  }
+  c->nB_csc = nB;
+  const bool priv_ok = c->E <= kMaxScatterLinks;
+  set_graph_shape(c, default_graph_ppl(c), default_link_sums(c));
+  const int64_t nBmax = std::max<int64_t>(nB, (c->E + 63) / 64);
   bool ok = dalloc(&c->d_i32, ni) == hipSuccess && dalloc(&c->d_Dn, c->D) == hipSuccess &&
             dalloc(&c->d_Cn, c->E) == hipSuccess && alloc_fwd(c->work, c) == hipSuccess &&
-            dalloc(&c->st.xf, c->P) == hipSuccess &&
-            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * nA1 * (kThreads / 64) * 4) == hipSuccess &&
-            dalloc(&c->st.partB, (size_t)2 * nB * 4) == hipSuccess &&
+            dalloc(&c->st.ctrl, 3) == hipSuccess && dalloc(&c->st.partA, (size_t)2 * partA_rows(c) * 4) == hipSuccess &&
+            dalloc(&c->st.partB, (size_t)2 * nBmax * 4) == hipSuccess &&
+            (!priv_ok || dalloc(&c->st.partL, (size_t)c->ncu * c->E) == hipSuccess) &&
+            dalloc(&c->st.w, c->E) == hipSuccess && dalloc(&c->st.dx2, c->P) == hipSuccess &&
             dalloc(&c->pb.xd, c->P) == hipSuccess && dalloc(&c->pb.S, c->D) == hipSuccess &&
             dalloc(&c->pb.L, c->E) == hipSuccess && dalloc(&c->pb.Cp, c->P) == hipSuccess &&
             dalloc(&c->pb.lsc, c->P) == hipSuccess && dalloc(&c->pb.trim, c->P) == hipSuccess &&
@@ -572,7 +668,14 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
       hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->pe[0]) != hipSuccess ||
       hipEventCreate(&c->pe[1]) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "event creation failed"));
-  c->st.nB = nB;
+  if (priv_ok) {
+    static bool prepared[64] = {false};
+    if (hip_device < 64 && !prepared[hip_device]) {
+      if (prepare_scatter_kernels() != hipSuccess)
+        return cleanup_fail(fail(TE_ERR_DEVICE, "LDS limit of the privatised-sum kernels could not be raised"));
+      prepared[hip_device] = true;
+    }
+  }
   {
     std::vector<int32_t> pool;
     pool.reserve(ni);
@@ -626,8 +729,6 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.wtab = c->d_wtab;
   p.hops = c->d_hops;
   p.H = c->d_hops ? c->H : 0;
-  p.ppl = c->ppl;
-  p.logGp = c->logGp;
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -644,6 +745,9 @@ te_status te_update(te_ctx *c, const double *capacity, const double *demand) {
   c->cap = cap;
   c->dem = dem;
   normalise(c);
+  // a recording describes the trajectory under the old capacities and demands: te_grad refuses it
+  c->rec_K = 0;
+  c->rec_gen++;
   return upload_values(c);
 }
 
@@ -658,6 +762,9 @@ te_status te_info(const te_ctx *c, int64_t *sz) {
   sz[6] = c->st.nA;
   sz[7] = c->st.nB;
   sz[8] = c->d_hops ? c->H : 0;
+  sz[9] = c->rec_K > 0 ? c->rec_gen : 0;
+  sz[10] = c->lsum;
+  sz[11] = c->prob.nF;
   return TE_OK;
 }
 
@@ -682,19 +789,36 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     if (engine == TE_ENGINE_BLOCK) return fail(TE_ERR_INVALID, "warm = 1 runs on the graph engine");
     engine = TE_ENGINE_GRAPH;
   }
+  if (o.per_link) engine = TE_ENGINE_GRAPH;
   if (engine == TE_ENGINE_AUTO) engine = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   if (engine == TE_ENGINE_BLOCK && c->lds_bytes > kMaxBlockLds)
     return fail(TE_ERR_INVALID, "instance needs %zu bytes of LDS, more than one workgroup has", c->lds_bytes);
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
+  // per-iteration trace (beta_k, alpha_k, r_k, s_k) of a solve that asks for it; a recorded solve
+  // writes the same rows into its recording log
+  const int kcap = o.fixed_iters > 0 ? o.fixed_iters : o.max_iters;
+  c->trace_engine = 0;
+  if (o.trace && !o.record) {
+    if (c->trace_cap < kcap) {
+      if (c->d_trace) HIPCHK(hipFree(c->d_trace));
+      c->d_trace = nullptr;
+      c->trace_cap = 0;
+      HIPCHK(dalloc(&c->d_trace, 4 * (size_t)kcap));
+      c->trace_cap = kcap;
+    }
+    c->trace_engine = engine;
+    c->trace_src = c->d_trace;
+    c->trace_src_cap = c->trace_cap;
+  }
   HIPCHK(hipEventRecord(c->ev0, stream));
   if (engine == TE_ENGINE_BLOCK) {
-    Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev};
+    Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev, o.trace ? c->d_trace : nullptr, o.trace ? c->trace_cap : 0};
     HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
                               c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads,
                               o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane, stream));
   } else {
-    s = select_graph_ppl(c, o);
+    s = select_graph_shape(c, o);
     if (s != TE_OK) return s;
     s = build_chunk_graph(c, stream);
     if (s != TE_OK) return s;
@@ -709,13 +833,16 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
       if (c->log_cap < o.fixed_iters) {
         if (c->d_log) HIPCHK(hipFree(c->d_log));
         c->d_log = nullptr;
-        HIPCHK(dalloc(&c->d_log, 2 * (size_t)o.fixed_iters));
+        c->log_cap = 0;
+        HIPCHK(dalloc(&c->d_log, 4 * (size_t)o.fixed_iters));
         c->log_cap = o.fixed_iters;
       }
       State sr = c->st;
-      sr.log_beta = c->d_log;
-      sr.log_alpha = c->d_log + c->log_cap;
+      sr.log = c->d_log;
       sr.log_cap = c->log_cap;
+      c->trace_engine = engine;  // the recording log doubles as the trace
+      c->trace_src = c->d_log;
+      c->trace_src_cap = c->log_cap;
       // checkpoints for te_grad every ck iterations: the state and the control record the next
       // iteration reads
       const int ck = o.ckpt_every > 0 ? o.ckpt_every : 16;
@@ -746,24 +873,41 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
         }
       }
       c->rec_K = o.fixed_iters;
+      c->rec_gen++;
       c->rec_ck = ck;
       c->rec_warm = x0_dev != nullptr;  // a given x^0 does not depend on the demands
     } else if (o.fixed_iters > 0) {
       const int K = o.fixed_iters;
+      State si = c->st;
+      hipGraphExec_t g = c->chunk;
+      if (o.trace) {
+        si.log = c->d_trace;
+        si.log_cap = c->trace_cap;
+        s = trace_graph(c, si, &g);
+        if (s != TE_OK) return s;
+      }
       while (launched + kChunk <= K) {
-        HIPCHK(hipGraphLaunch(c->chunk, stream));
+        HIPCHK(hipGraphLaunch(g, stream));
         launched += kChunk;
       }
       while (launched < K) {
-        HIPCHK(launch_iteration(c->prob, c->st, c->d_params, launched & 1, stream));
+        HIPCHK(launch_iteration(c->prob, si, c->d_params, launched & 1, stream));
         ++launched;
       }
     } else {
       // adaptive: chunks until the device-side stop flag is seen (one chunk in flight ahead)
       const int K = o.max_iters;
+      hipGraphExec_t g = c->chunk;
+      if (o.trace) {
+        State si = c->st;
+        si.log = c->d_trace;
+        si.log_cap = c->trace_cap;
+        s = trace_graph(c, si, &g);
+        if (s != TE_OK) return s;
+      }
       bool stopped = false;
       while (launched < K && !stopped) {
-        HIPCHK(hipGraphLaunch(c->chunk, stream));
+        HIPCHK(hipGraphLaunch(g, stream));
         launched += kChunk;
         const int slot = (launched / kChunk) & 1;
         HIPCHK(hipMemcpyAsync(&c->h_flag[slot], &c->st.ctrl[(launched - 1) & 1].stop, sizeof(int32_t),
@@ -777,7 +921,12 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
       }
     }
     const int last_par = launched > 0 ? (launched - 1) & 1 : 1;
-    HIPCHK(launch_finish(c->st, c->d_params, last_par, stream));
+    State sf = c->st;
+    if (c->trace_engine) {
+      sf.log = c->trace_src;
+      sf.log_cap = c->trace_src_cap;
+    }
+    HIPCHK(launch_finish(sf, c->d_params, last_par, stream));
     HIPCHK(launch_project(c->prob, c->st, c->pb, x_out_dev, S_out_dev, c->scale, o.project, stream));
   }
   HIPCHK(hipEventRecord(c->ev1, stream));
@@ -820,7 +969,7 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
   hipStream_t stream = (hipStream_t)hip_stream;
   DeviceScope dscope(c->device);
   HIPCHK(dscope.err);
-  s = select_graph_ppl(c, o);
+  s = select_graph_shape(c, o);
   if (s != TE_OK) return s;
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
@@ -832,6 +981,7 @@ te_status te_kernel_times(te_ctx *c, const te_options *opt, void *hip_stream, in
       return fail(TE_ERR_DEVICE, "event creation failed");
     }
   c->state_scale = 0.0;  // this run overwrites the state a warm restart would continue from
+  c->trace_engine = 0;   // and the control record a trace is read with
   hipError_t err = launch_init(c->prob, c->st, c->d_params, nullptr, 1.0 / c->scale, stream);
   for (int k = 0; k < iters && err == hipSuccess; ++k) {
     err = launch_demand_timed(c->prob, c->st, c->d_params, k & 1, stream, ev[4 * k], ev[4 * k + 1]);
@@ -866,6 +1016,20 @@ te_status te_project(te_ctx *c, void *hip_stream, float *x_out_dev, float *S_out
   return TE_OK;
 }
 
+te_status te_get_state(te_ctx *c, void *hip_stream, double *x_out_dev, double *S_out_dev, double *w_out_dev) {
+  if (!c || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or output");
+  if (c->state_scale <= 0.0) return fail(TE_ERR_STATE, "no graph-engine state on this handle");
+  if (c->state_scale != c->scale)
+    return fail(TE_ERR_STATE, "te_update changed the unit scale since the last solve (continue with warm = 1 first)");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
+  HIPCHK(launch_get_state(c->prob, c->st, c->scale, x_out_dev, S_out_dev, stream));
+  if (w_out_dev)
+    HIPCHK(hipMemcpyAsync(w_out_dev, c->st.w, sizeof(double) * c->E, hipMemcpyDeviceToDevice, stream));
+  return TE_OK;
+}
+
 te_status te_project_rates(te_ctx *c, void *hip_stream, const float *x_in_dev, double alpha, float *x_out_dev,
                            float *S_out_dev) {
   if (!c || !x_in_dev || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or buffer");
@@ -874,6 +1038,32 @@ te_status te_project_rates(te_ctx *c, void *hip_stream, const float *x_in_dev, d
   DeviceScope dscope(c->device);
   HIPCHK(dscope.err);
   HIPCHK(launch_project_rates(c->prob, c->pb, x_in_dev, alpha, x_out_dev, S_out_dev, c->scale, stream));
+  return TE_OK;
+}
+
+te_status te_trace(te_ctx *c, void *hip_stream, int32_t cap, double *out, int32_t *n_out) {
+  if (!c || !out || !n_out || cap < 0) return fail(TE_ERR_INVALID, "null handle or buffer, or cap < 0");
+  *n_out = 0;
+  if (!c->trace_engine) return fail(TE_ERR_STATE, "the handle's last solve ran without trace = 1 or record = 1");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
+  HIPCHK(hipStreamSynchronize(stream));
+  int32_t k = 0;
+  if (c->trace_engine == TE_ENGINE_BLOCK) {
+    BatchOut bo;
+    HIPCHK(hipMemcpy(&bo, c->d_bout, sizeof(bo), hipMemcpyDeviceToHost));
+    k = bo.iters;
+  } else {
+    Ctrl fin;
+    HIPCHK(hipMemcpy(&fin, c->st.ctrl + 2, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    k = fin.k;
+  }
+  const int32_t n = std::min(std::min(k, c->trace_src_cap), cap);
+  for (int row = 0; row < 4 && n > 0; ++row)
+    HIPCHK(hipMemcpy(out + (size_t)row * cap, c->trace_src + (size_t)row * c->trace_src_cap, sizeof(double) * n,
+                     hipMemcpyDeviceToHost));
+  *n_out = n;
   return TE_OK;
 }
 
@@ -922,6 +1112,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
   if (s != TE_OK) return s;
   HIPCHK(hipStreamSynchronize(stream));  // the host schedule arrays are local to this call
   c->state_scale = 0.0;  // the segment recomputation overwrites the state a warm restart would continue from
+  c->trace_engine = 0;   // and the control record a trace is read with
   // reverse, segment by segment: restore the segment's checkpoint, recompute its iterations with
   // the recorded schedule keeping every state, then run the adjoint iterations backwards
   HIPCHK(launch_adj_seed(c->prob, a, dS_dev, stream));
@@ -947,7 +1138,7 @@ te_status te_grad(te_ctx *c, void *hip_stream, const float *dS_dev, double *dC_d
     }
     for (int k = k1 - 1; k >= k0; --k) {
       const double rho = k > 0 ? lb[k - 1] / lb[k] : 1.0;
-      HIPCHK(launch_adj_iteration(c->prob, c->st.nB, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
+      HIPCHK(launch_adj_iteration(c->prob, c->nB_csc, c->seg[k - k0], c->seg[k - k0 + 1], a, lb[k],
                                   la[k], rho, stream));
     }
   }
@@ -960,6 +1151,7 @@ void te_destroy(te_ctx *c) {
   DeviceScope dscope(c->device);
   if (c->chunk) (void)hipGraphExecDestroy(c->chunk);
   if (c->rec_chunk) (void)hipGraphExecDestroy(c->rec_chunk);
+  if (c->trace_chunk) (void)hipGraphExecDestroy(c->trace_chunk);
   for (auto &f : c->ckpt) free_fwd(f);
   for (auto &f : c->seg) free_fwd(f);
   for (Ctrl *p : c->ckpt_ctrl)
@@ -970,7 +1162,7 @@ void te_destroy(te_ctx *c) {
       if (p) (void)hipFree(p);
   }
   free_fwd(c->work);
-  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->st.xf, c->st.ctrl,
+  void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->d_trace, c->st.partL, c->st.w, c->st.dx2, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
                   c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops};
   for (void *b : bufs)
@@ -1078,7 +1270,7 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
   hipStream_t stream = (hipStream_t)hip_stream;
   DeviceScope dscope(b->device);
   HIPCHK(dscope.err);
-  Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr};
+  Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr, nullptr, 0};
   int threads = o.block_threads, ppl = o.paths_per_lane;
   if (threads == 0 || ppl == 0) {
     const std::pair<int, int> key(threads, ppl);

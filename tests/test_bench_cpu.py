@@ -43,18 +43,42 @@ def test_traffic_missing_file(monkeypatch, tmp_path):
     assert bench.measured_traffic("k_demand") is None
 
 
-def test_kernel_bytes_by_counting():
-    """Byte counts of the smallest builder instance, tallied array by array from its sizes."""
+def test_b_iter_by_counting():
+    """The algorithmic bytes of one iteration, tallied array by array on the smallest builder instance:
+    B_iter = 4 nnz + 4 (P + 1) + 16 P + 16 D + 40 E, split into the demand step and the link step."""
     inst = W.parking_lot(3)
     P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
-    # demand kernel: link ids, x and u_neg (FP64) read and written, FP32 x written, (g, q) per link,
-    # per demand: range pointer, demand, u_dem and S read and written
-    for H in (0, 4, 8):
-        ids = 2 * H * P if H else 4 * (P + 1) + 4 * nnz
-        dem = ids + (8 + 8) * 2 * P + 4 * P + 16 * E + (4 + 8 + 2 * 8 + 2 * 8) * D
-        # link kernel: CSC path ids, FP32 x, (g, q) read and written, capacity, non-empty link tables
-        link = 4 * nnz + 4 * P + 2 * 16 * E + 8 * E + 8 * E
-        assert bench.kernel_bytes(inst, H) == (dem, link)
+    # demand step: int32 link ids, int32 row pointers, FP32 x and u_neg each read and written,
+    # per demand FP32 D, u_dem read and written, int32 range pointer
+    dem = 4 * nnz + 4 * (P + 1) + 2 * 4 * 2 * P + (4 + 2 * 4 + 4) * D
+    # link step: FP32 C, g and q each read and written, int32 n_e, the FP64 load written and read
+    link = (4 + 2 * 4 + 2 * 4 + 4 + 2 * 8) * E
+    assert bench.b_iter_shares(inst) == (dem, link)
+    assert sum(bench.b_iter_shares(inst)) == 4 * nnz + 4 * (P + 1) + 16 * P + 16 * D + 40 * E
+
+
+def test_layout_bytes_by_counting():
+    """This build's own bytes per launch, both link-sum variants, on the smallest builder instance."""
+    inst = W.parking_lot(3)
+    P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
+    for hop in (0, 4):
+        ids = 2 * nnz if hop else 4 * (P + 1) + 4 * nnz
+        base = ids + (8 + 8) * 2 * P + 16 * E + (4 + 8 + 2 * 8 + 2 * 8) * D
+        priv = dict(hop_slots=hop, link_sums=1, scatter_workgroups=3)
+        rows = 3 * 8 * E
+        assert bench.layout_bytes(inst, priv) == (base + rows, rows + 2 * 16 * E + 8 * E + 8 * E)
+        csc = dict(hop_slots=hop, link_sums=2, scatter_workgroups=0)
+        assert bench.layout_bytes(inst, csc) == (base, 4 * nnz + 8 * P + 2 * 16 * E + 8 * E + 8 * E)
+
+
+def test_roofline_fractions():
+    inst = W.parking_lot(3)
+    info = dict(hop_slots=4, link_sums=1, scatter_workgroups=2)
+    names, k, it = bench.roofline_of(inst, info, 1e-3, 1e-3)
+    assert names == ("k_demand_scatter", "k_link_reduce")
+    a_dem, a_link = bench.b_iter_shares(inst)
+    assert k["k_demand_scatter"]["achieved_gbs"] == round(a_dem / 1e-6 / 1e9, 2)
+    assert it["frac"] == round((a_dem + a_link) / 2e-6 / 1e9 / bench.HBM_PEAK_GBS, 5)
 
 
 def test_optimality_metric_special_cases():

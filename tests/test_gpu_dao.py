@@ -3,7 +3,8 @@ and of the drift-adjusted optimality built on it (section 4.1), against the FP64
 and exact max-min allocations of the drifted states.
 
 The bar for the applied rates is the one of the projection tests: the oracle's Algorithm 2 on the
-same FP32 input rates, to 2e-6 relative (the GPU rounds its FP32 outputs toward zero).
+same FP32 input rates, to 2e-6 relative (the GPU rounds its FP32 outputs toward zero), except for
+paths whose trim order FP32 scores do not resolve (tests/projcheck.py).
 """
 import os
 
@@ -12,6 +13,7 @@ import pytest
 
 import oracle as O
 import workloads as W
+from projcheck import check_projection
 
 pytestmark = pytest.mark.gpu
 
@@ -70,11 +72,9 @@ def test_project_rates_matches_oracle_under_drift(te, c1, solved_c1, drifted_c1)
         prob.update(capacity=inst.capacity, demand=inst.demand)
         xa, Sa = prob.project_rates(x0, alpha)
         xa = xa.cpu().numpy().astype(np.float64)
-        ref = O.project(inst, x0.astype(np.float64), alpha)
-        print(f"{inst.name}: applied throughput {xa.sum():.4f} of {x0.sum():.4f}; "
-              f"max |dx| {np.abs(xa - ref).max():.2e}")
+        print(f"{inst.name}: applied throughput {xa.sum():.4f} of {x0.sum():.4f}")
         _check_feasible(inst, xa, x0)
-        np.testing.assert_allclose(xa, ref, rtol=2e-6, atol=1e-6 * inst.capacity.max())
+        check_projection(inst, x0, xa, alpha, tag=inst.name)
         np.testing.assert_allclose(Sa.cpu().numpy(), O.demand_sums(inst, xa), rtol=1e-6)
     # at T_0 the solve's own (feasible) allocation comes back unchanged
     prob.update(capacity=c1.capacity, demand=c1.demand)
@@ -93,9 +93,7 @@ def test_project_rates_waxman150(te):
     xa, Sa = prob.project_rates(x0, st["final_alpha"])
     xa = xa.cpu().numpy().astype(np.float64)
     _check_feasible(inst, xa, x0)
-    ref = O.project(inst, x0.astype(np.float64), st["final_alpha"])
-    np.testing.assert_allclose(O.demand_sums(inst, xa), O.demand_sums(inst, ref), rtol=1e-5,
-                               atol=1e-6 * inst.capacity.max())
+    check_projection(inst, x0, xa, st["final_alpha"], tag="waxman150 drifted 300 s")
 
 
 def test_project_rates_ragged_and_in_place(te, torch):
@@ -111,8 +109,7 @@ def test_project_rates_ragged_and_in_place(te, torch):
         xa, _ = prob.project_rates(x0, alpha)
         xa = xa.cpu().numpy().astype(np.float64)
         _check_feasible(inst, xa, x0.astype(np.float64))
-        ref = O.project(inst, x0.astype(np.float64), alpha)
-        np.testing.assert_allclose(xa, ref, rtol=2e-6, atol=1e-6 * inst.capacity.max())
+        check_projection(inst, x0, xa, alpha, tag=f"ragged alpha={alpha}")
         xt = torch.tensor(x0, device="cuda")
         xi, _ = prob.project_rates(xt, alpha, x_out=xt)
         assert xi.data_ptr() == xt.data_ptr()
