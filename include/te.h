@@ -235,6 +235,20 @@ te_status te_project_rates(te_ctx *ctx, void *hip_stream, const float *x_in_dev,
                            float *S_out_dev);
 
 /*
+ * te_project_rates without allocating: for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * semantics and results as te_project_rates, but the projection's working arrays (24 P + 8 D + 8 E
+ * bytes, each array rounded up to 256 bytes) come from a static device array of 32 MiB that every
+ * GPU the library runs on holds until the process ends, not from the handle.  All calls on one GPU
+ * share that array: calls that overlap on one GPU (on different streams or threads) race and must
+ * be ordered by the caller.  Every array is rewritten before it is read, so nothing of an earlier
+ * call's contents carries over.  Calls no hipMalloc/hipFree.
+ * TE_ERR_INVALID if the instance needs more scratch than the array holds, or as te_project_rates.
+ */
+te_status te_project_rates_static(te_ctx *ctx, void *hip_stream, const float *x_in_dev, double alpha,
+                                  float *x_out_dev, float *S_out_dev);
+
+/*
  * Vector-Jacobian product through the last solve run with opt->record = 1 and
  * opt->fixed_iters = K: the unprojected sums S^(K) as a function of capacities
  * and demands, with the recorded (beta, alpha) schedule and the unit scale

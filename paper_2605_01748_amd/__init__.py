@@ -22,7 +22,7 @@ ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
 LINK_SUMS_AUTO, LINK_SUMS_PRIVATE, LINK_SUMS_CSC = 0, 1, 2
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
-       "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_get_state", "te_trace", "te_destroy", "te_destroy_batch",
+       "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_project_rates_static", "te_get_state", "te_trace", "te_destroy", "te_destroy_batch",
        "te_info", "te_last_error"]
 
 
@@ -91,6 +91,8 @@ def library(path: str = LIB_PATH):
     lib.te_project.argtypes = [P, P, P, P]
     lib.te_project_rates.restype = I
     lib.te_project_rates.argtypes = [P, P, P, ctypes.c_double, P, P]
+    lib.te_project_rates_static.restype = I
+    lib.te_project_rates_static.argtypes = [P, P, P, ctypes.c_double, P, P]
     lib.te_get_state.restype = I
     lib.te_get_state.argtypes = [P, P, P, P, P]
     lib.te_trace.restype = I
@@ -299,10 +301,12 @@ class Problem:
         _check(library().te_get_state(self._h, sp, x.data_ptr(), S.data_ptr(), None if w is None else w.data_ptr()))
         return (x, S, w) if with_w else (x, S)
 
-    def project_rates(self, x, alpha, x_out=None, S_out=None, stream=None):
+    def project_rates(self, x, alpha, x_out=None, S_out=None, stream=None, static_scratch=False):
         """Algorithm 2 applied to the given path rates x (caller units) under the handle's current
-        capacities and demands, with trim scores at `alpha` (te_project_rates): returns (x [n_paths],
-        S [n_demands]) float32 cuda tensors in caller units."""
+        capacities and demands, with trim scores at `alpha` (te_project_rates, or with
+        static_scratch=True te_project_rates_static, whose working arrays live in the library's
+        static device array): returns (x [n_paths], S [n_demands]) float32 cuda tensors in caller
+        units."""
         import torch
         dev = torch.device("cuda", self.device)
         x = torch.as_tensor(x).to(device=dev, dtype=torch.float32).contiguous()
@@ -313,8 +317,8 @@ class Problem:
         if S_out is None:
             S_out = torch.empty(self.n_demands, dtype=torch.float32, device=dev)
         sp = _stream_ptr(dev) if stream is None else stream
-        _check(library().te_project_rates(self._h, sp, x.data_ptr(), float(alpha), x_out.data_ptr(),
-                                          S_out.data_ptr()))
+        fn = library().te_project_rates_static if static_scratch else library().te_project_rates
+        _check(fn(self._h, sp, x.data_ptr(), float(alpha), x_out.data_ptr(), S_out.data_ptr()))
         return x_out, S_out
 
     def kernel_times(self, opts: Options | None = None, iters: int = 64, stream=None):

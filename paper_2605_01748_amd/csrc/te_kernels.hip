@@ -18,6 +18,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "te_device.h"
 #include "te_internal.h"
 
@@ -1879,6 +1881,39 @@ hipError_t launch_project(const Prob &p, const State &s, const ProjBuf &b, float
   }
   hipLaunchKernelGGL(kp_output, dim3(nD), dim3(256), 0, st, p, b, x_out, S_out, scale, project, s.x);
   return hipGetLastError();
+}
+
+// Scratch of te_project_rates_static, the entry point that allocates nothing: the projection's
+// working arrays carved from one file-scope device array of kStaticScratchBytes.  Every GPU the
+// library runs on holds its own copy until the process ends; all calls on one GPU share it (calls
+// that overlap on one GPU race).  In host code `scratch` only names the array: its device address
+// comes from hipGetSymbolAddress, once per device, kept in g_scratch.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {nullptr};
+}  // namespace
+
+// Device address and size of the current device's copy of the static scratch (looked up on the
+// first call per device, with that device current).
+hipError_t static_scratch(void **out, size_t *bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = ptr;
+  }
+  *out = g_scratch[dev];
+  *bytes = kStaticScratchBytes;
+  return hipSuccess;
 }
 
 // Algorithm 2 on caller rates x_in (caller units) at the given alpha; x_out may alias x_in

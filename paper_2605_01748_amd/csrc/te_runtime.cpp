@@ -38,6 +38,7 @@ hipError_t launch_adj_iteration(const Prob &, int, const FwdState &, const FwdSt
 hipError_t launch_adj_x0(const Prob &, const AdjState &, hipStream_t);
 hipError_t prepare_scatter_kernels();
 hipError_t launch_get_state(const Prob &, const State &, double, double *, double *, hipStream_t);
+hipError_t static_scratch(void **, size_t *);
 }  // namespace te
 
 using namespace te;
@@ -668,6 +669,12 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
       hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->pe[0]) != hipSuccess ||
       hipEventCreate(&c->pe[1]) != hipSuccess)
     return cleanup_fail(fail(TE_ERR_DEVICE, "event creation failed"));
+  {
+    void *sb = nullptr;  // the static scratch of te_project_rates_static: address looked up once per device
+    size_t sbytes = 0;
+    if (static_scratch(&sb, &sbytes) != hipSuccess)
+      return cleanup_fail(fail(TE_ERR_DEVICE, "address of the static scratch could not be looked up"));
+  }
   if (priv_ok) {
     static bool prepared[64] = {false};
     if (hip_device < 64 && !prepared[hip_device]) {
@@ -1016,6 +1023,26 @@ te_status te_project(te_ctx *c, void *hip_stream, float *x_out_dev, float *S_out
   return TE_OK;
 }
 
+// The projection's working arrays (ProjBuf) carved from a scratch region at `base`, each part
+// 256-byte aligned; returns the bytes used.
+size_t carve_projbuf(void *base, int32_t P, int32_t D, int32_t E, ProjBuf *b) {
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    const size_t at = off;
+    off += (n + 255) & ~size_t(255);
+    return base ? static_cast<unsigned char *>(base) + at : nullptr;
+  };
+  ProjBuf r{};
+  r.xd = reinterpret_cast<double *>(take(sizeof(double) * (size_t)P));
+  r.S = reinterpret_cast<double *>(take(sizeof(double) * (size_t)D));
+  r.L = reinterpret_cast<double *>(take(sizeof(double) * (size_t)E));
+  r.Cp = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)P));
+  r.lsc = reinterpret_cast<float *>(take(sizeof(float) * (size_t)P));
+  r.trim = reinterpret_cast<uint64_t *>(take(sizeof(uint64_t) * (size_t)P));
+  if (b) *b = r;
+  return off;
+}
+
 te_status te_get_state(te_ctx *c, void *hip_stream, double *x_out_dev, double *S_out_dev, double *w_out_dev) {
   if (!c || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or output");
   if (c->state_scale <= 0.0) return fail(TE_ERR_STATE, "no graph-engine state on this handle");
@@ -1064,6 +1091,26 @@ te_status te_trace(te_ctx *c, void *hip_stream, int32_t cap, double *out, int32_
     HIPCHK(hipMemcpy(out + (size_t)row * cap, c->trace_src + (size_t)row * c->trace_src_cap, sizeof(double) * n,
                      hipMemcpyDeviceToHost));
   *n_out = n;
+  return TE_OK;
+}
+
+te_status te_project_rates_static(te_ctx *c, void *hip_stream, const float *x_in_dev, double alpha,
+                                  float *x_out_dev, float *S_out_dev) {
+  if (!c || !x_in_dev || !x_out_dev) return fail(TE_ERR_INVALID, "null handle or buffer");
+  if (!std::isfinite(alpha) || alpha < 0.0) return fail(TE_ERR_INVALID, "alpha must be finite and >= 0");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  DeviceScope dscope(c->device);
+  HIPCHK(dscope.err);
+  void *base = nullptr;
+  size_t cap = 0;
+  HIPCHK(static_scratch(&base, &cap));
+  const size_t need = carve_projbuf(nullptr, c->P, c->D, c->E, nullptr);
+  if (need > cap)
+    return fail(TE_ERR_INVALID, "te_project_rates_static: the instance needs %zu bytes of scratch, the static "
+                                "scratch holds %zu (24 P + 8 D + 8 E bytes, rounded per array)", need, cap);
+  ProjBuf b;
+  carve_projbuf(base, c->P, c->D, c->E, &b);
+  HIPCHK(launch_project_rates(c->prob, b, x_in_dev, alpha, x_out_dev, S_out_dev, c->scale, stream));
   return TE_OK;
 }
 
