@@ -263,10 +263,16 @@ te_status te_project_rates_static(te_ctx *ctx, void *hip_stream, const float *x_
 te_status te_grad(te_ctx *ctx, void *hip_stream, const float *dS_dev, double *dC_dev, double *dD_dev);
 
 /*
- * Batched solves: n instances (handles on the same device, used read-only) in one
- * launch of the workgroup engine, one workgroup per instance, each with its own
- * beta / alpha / stop state.  Instances too large for one workgroup's LDS are
- * rejected with TE_ERR_INVALID.
+ * Batched solves: n instances (handles on the same device, used read-only) in one launch.
+ *  - Workgroup engine (opt->engine BLOCK, or AUTO when every instance fits one workgroup's LDS):
+ *    one workgroup per instance, each with its own beta / alpha / stop state.
+ *  - Graph engine (opt->engine GRAPH, AUTO when some instance does not fit, or per_link): the
+ *    instances' disjoint union as one instance (built on the first such solve), each instance in
+ *    its own normalised units.  The union shares one beta / alpha schedule and one stop, driven by
+ *    the union's residuals; as the instances share no link or demand, each one's iterates are
+ *    exactly those of its own solve under that schedule, and its optimum (max-min or alpha-fair) is
+ *    its own.  Every te_stats entry then holds the union's control.
+ * BLOCK with an instance that does not fit returns TE_ERR_INVALID.  No warm, record or trace.
  */
 te_status te_create_batch(int32_t n, te_ctx *const *instances, te_batch **out);
 

@@ -74,6 +74,9 @@ struct Prob {
   // privatised sums: passes of kScatThreads / 2^logGp demands, spw consecutive passes per scatter
   // workgroup, nF workgroups (rows of partial loads)
   int32_t npass, spw, nF;
+  // nullable [D]: per-demand unit scale of the outputs (a batch solved as the union of its
+  // instances, each in its own units), in place of the handle's one scale
+  const double *dscale;
 };
 
 enum { kLinkSumsPrivate = 1, kLinkSumsCsc = 2 };

@@ -1010,6 +1010,7 @@ __global__ void kp_clamp_sums_in(Prob p, const float *x_in, double scale, ProjBu
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
+    if (p.dscale) scale = p.dscale[c];
     double sum = 0.0;
     for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
       const double v = fmax((double)x_in[r] / scale, 0.0);
@@ -1243,6 +1244,7 @@ __global__ void kp_output(Prob p, ProjBuf b, float *x_out, float *S_out, double 
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
+    if (p.dscale) scale = p.dscale[c];
     double sum = 0.0;
     for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
       if (project) {
@@ -1264,6 +1266,7 @@ __global__ void k_get_state(Prob p, State s, double scale, double *x_out, double
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int nth = gridDim.x * blockDim.x;
   for (int c = tid; c < p.D; c += nth) {
+    if (p.dscale) scale = p.dscale[c];
     double sum = 0.0;
     for (int r = p.dptr[c]; r < p.dptr[c + 1]; ++r) {
       x_out[r] = s.x[r] * scale;

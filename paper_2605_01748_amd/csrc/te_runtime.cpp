@@ -171,6 +171,13 @@ struct te_batch {
   // (block_threads, paths_per_lane) picked on the first solve that leaves one or both at 0, per
   // requested pair
   std::map<std::pair<int, int>, std::pair<int, int>> tuned;
+  // every instance fits one workgroup's LDS (else only the graph engine runs the batch)
+  bool all_fit = true;
+  std::vector<te_ctx *> members;
+  // the graph engine's batch: one handle on the disjoint union of the instances, each in its own
+  // normalised units, built on the first solve that uses it; per-demand output scales
+  te_ctx *uni = nullptr;
+  double *d_dscale = nullptr;
 };
 
 extern "C" {
@@ -1245,10 +1252,8 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
       delete b;
       return fail(TE_ERR_INVALID, "batch instance %d is null or on another device", k);
     }
-    if (c->lds_bytes > kMaxBlockLds) {
-      delete b;
-      return fail(TE_ERR_INVALID, "batch instance %d needs %zu bytes of LDS", k, c->lds_bytes);
-    }
+    b->members.push_back(inst[k]);
+    if (c->lds_bytes > kMaxBlockLds) b->all_fit = false;
     BatchDesc d{};
     d.E = c->E;
     d.P = c->P;
@@ -1278,7 +1283,7 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
     offE += c->E;
     offP += c->P;
     offD += c->D;
-    b->lds_bytes = std::max(b->lds_bytes, c->lds_bytes);
+    if (c->lds_bytes <= kMaxBlockLds) b->lds_bytes = std::max(b->lds_bytes, c->lds_bytes);
     b->desc.push_back(d);
   }
   b->totP = offP;
@@ -1307,6 +1312,39 @@ te_status te_create_batch(int32_t n, te_ctx *const *inst, te_batch **out) {
   return TE_OK;
 }
 
+// The disjoint union of a batch's instances as one handle: link, path and demand ids offset, every
+// instance's capacities and demands in its own normalised units (so the union's unit scale is 1 and
+// each instance iterates exactly as alone under the union's (beta, alpha) schedule), outputs scaled
+// back per demand.
+te_status build_union(te_batch *b) {
+  std::vector<double> cap, dem, dsc;
+  std::vector<int64_t> pptr(1, 0);
+  std::vector<int32_t> plinks, dptr(1, 0);
+  int32_t offE = 0, offP = 0;
+  for (const te_ctx *c : b->members) {
+    cap.insert(cap.end(), c->Cn.begin(), c->Cn.end());
+    dem.insert(dem.end(), c->Dn.begin(), c->Dn.end());
+    dsc.insert(dsc.end(), (size_t)c->D, c->scale);
+    for (int32_t r = 0; r < c->P; ++r) pptr.push_back(pptr.back() + (c->pptr[r + 1] - c->pptr[r]));
+    for (int32_t i = 0; i < c->nnz; ++i) plinks.push_back(c->plinks[i] + offE);
+    for (int32_t k = 1; k <= c->D; ++k) dptr.push_back(c->dptr[k] + offP);
+    offE += c->E;
+    offP += c->P;
+  }
+  te_ctx *u = nullptr;
+  te_status s = te_create(offE, cap.data(), offP, pptr.data(), plinks.data(), (int32_t)dem.size(), dptr.data(),
+                          dem.data(), b->device, &u);
+  if (s != TE_OK) return s;
+  if (dalloc(&b->d_dscale, dsc.size()) != hipSuccess ||
+      hipMemcpy(b->d_dscale, dsc.data(), sizeof(double) * dsc.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    te_destroy(u);
+    return fail(TE_ERR_OOM, "union scale upload failed");
+  }
+  u->prob.dscale = b->d_dscale;  // before any capture: the captured launches hold the Prob
+  b->uni = u;
+  return TE_OK;
+}
+
 te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, float *x_out_dev, float *S_out_dev,
                          te_stats *stats) {
   if (!b || !x_out_dev) return fail(TE_ERR_INVALID, "null batch or output");
@@ -1317,6 +1355,24 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
   hipStream_t stream = (hipStream_t)hip_stream;
   DeviceScope dscope(b->device);
   HIPCHK(dscope.err);
+  if (o.warm || o.record || o.trace) return fail(TE_ERR_INVALID, "batches take no warm, record or trace");
+  const bool graph = o.engine == TE_ENGINE_GRAPH || o.per_link || (o.engine == TE_ENGINE_AUTO && !b->all_fit);
+  if (!graph && !b->all_fit)
+    return fail(TE_ERR_INVALID, "an instance of the batch does not fit one workgroup's LDS (use the graph engine)");
+  if (graph) {
+    if (!b->uni) {
+      s = build_union(b);
+      if (s != TE_OK) return s;
+    }
+    te_options g = o;
+    g.engine = TE_ENGINE_GRAPH;
+    te_stats st{};
+    s = te_solve(b->uni, &g, hip_stream, nullptr, x_out_dev, S_out_dev, stats ? &st : nullptr);
+    if (s != TE_OK) return s;
+    if (stats)
+      for (int32_t k = 0; k < b->n; ++k) stats[k] = st;
+    return TE_OK;
+  }
   Pools pools{b->d_i32, b->d_Dn, b->d_Cn, nullptr, nullptr, 0};
   int threads = o.block_threads, ppl = o.paths_per_lane;
   if (threads == 0 || ppl == 0) {
@@ -1392,8 +1448,9 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
 
 void te_destroy_batch(te_batch *b) {
   if (!b) return;
+  if (b->uni) te_destroy(b->uni);
   DeviceScope dscope(b->device);
-  void *bufs[] = {b->d_desc, b->d_out, b->d_i32, b->d_Dn, b->d_Cn, b->d_params, b->d_sched};
+  void *bufs[] = {b->d_desc, b->d_out, b->d_i32, b->d_Dn, b->d_Cn, b->d_params, b->d_sched, b->d_dscale};
   for (void *p : bufs)
     if (p) (void)hipFree(p);
   if (b->h_params) (void)hipHostFree(b->h_params);

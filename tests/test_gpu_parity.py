@@ -808,3 +808,56 @@ def test_per_link_refused_where_unsupported(te, c1):
         with pytest.raises(te.TEError) as ex:
             prob.solve(te.Options(per_link=True, **{"fixed_iters": 8, **bad}))
         assert ex.value.status == te.TE_ERR_INVALID
+
+
+def test_mixed_batch_runs_as_union_on_graph_engine(te):
+    """A batch of 20-node failure scenarios and the 150-node instance (too large for one workgroup):
+    one graph-engine solve of the instances' disjoint union, each instance in its own units.  Each
+    instance's sums equal the oracle's solve of the same union (per-demand bar), its projected rates
+    are feasible, and the workgroup engine refuses the batch."""
+    from test_oracle_union import union_normalised
+    small = W.failure_scenarios(0, n_scen=5)
+    insts = small[:2] + [W.waxman150(0)] + small[2:]
+    batch = te.Batch([te.Problem(i) for i in insts])
+    K = 200
+    _, S, st = batch.solve(te.Options(fixed_iters=K, project=False))
+    assert all(s["engine"] == te.ENGINE_GRAPH and s["iters"] == K for s in st)
+    S = S.cpu().numpy().astype(np.float64)
+    u, scales = union_normalised(insts)
+    r = O.solve(u, O.Options(fixed_iters=K, project=False), want_state=False)
+    off = 0
+    for inst, s in zip(insts, scales):
+        err = _report(f"union member {inst.name}", S[off:off + inst.n_demands],
+                      r.S_raw[off:off + inst.n_demands] * s, inst.demand)
+        assert err.max() <= REL
+        off += inst.n_demands
+    xp, Sp, _ = batch.solve(te.Options(fixed_iters=K))
+    xp = xp.cpu().numpy().astype(np.float64)
+    offP = 0
+    for inst in insts:
+        xi = xp[offP:offP + inst.n_paths]
+        assert np.all(xi >= 0)
+        assert np.all(O.link_loads(inst, xi) <= inst.capacity * (1 + 1e-7))
+        assert np.all(O.demand_sums(inst, xi) <= inst.demand * (1 + 1e-7))
+        offP += inst.n_paths
+    with pytest.raises(te.TEError) as ex:
+        batch.solve(te.Options(fixed_iters=8, engine=te.ENGINE_BLOCK))
+    assert ex.value.status == te.TE_ERR_INVALID
+
+
+def test_small_batch_on_graph_engine_reaches_maxmin(te):
+    """The failure scenarios forced onto the graph engine's union: every scenario within 1 % of its own
+    exact max-min allocation (tests/golden), like the workgroup engine's batch."""
+    g = np.load(_golden("maxmin_failures_s0.npz"))
+    scen = W.failure_scenarios(0, n_scen=32)
+    batch = te.Batch([te.Problem(s) for s in scen])
+    _, S, st = batch.solve(te.Options(fixed_iters=1000, engine=te.ENGINE_GRAPH))
+    assert st[0]["engine"] == te.ENGINE_GRAPH
+    S = S.cpu().numpy().astype(np.float64)
+    off, worst = 0, 1.0
+    for i, inst in enumerate(scen):
+        assert str(g[f"fp{i}"]) == inst.fingerprint()
+        worst = min(worst, O.optimality(S[off:off + inst.n_demands], g[f"S{i}"], 1e-9 * 100.0))
+        off += inst.n_demands
+    print(f"32 failure scenarios as one union, 1000 iterations: worst optimality {worst:.5f}")
+    assert worst >= 0.99
