@@ -50,6 +50,7 @@ def log(*a):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_demand_k_link_150node_traffic.md")
+TRAFFIC_FILE_LARGE = os.path.join(ROOT, "profiles", "k_demand_scatter_k_link_reduce_1000node_traffic.md")
 
 
 def cpu_model():
@@ -79,13 +80,13 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, path=None):
     """HBM bytes per dispatch of `kernel` from the committed counter summary (FETCH_SIZE and WRITE_SIZE,
     each scaled by the same counter's reading for a copy of known size), or None when the summary is
     missing or was taken on other kernel sources."""
     import re
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path or TRAFFIC_FILE) as fh:
             m = re.search(r"```json\n(.*?)\n```", fh.read(), re.S)
         d = json.loads(m.group(1))
     except (OSError, AttributeError, ValueError):
@@ -94,6 +95,16 @@ def measured_traffic(kernel):
         return None
     k = d.get("kernels", {}).get(kernel)
     return None if k is None else int(k["traffic_bytes"])
+
+
+def profiled_name(kernel, ppl):
+    """The name a profile gives a per-iteration kernel: the demand kernels carry their paths per lane
+    as a template argument."""
+    if kernel == "k_demand_scatter":
+        return f"k_demand_scatter<{ppl}>"
+    if kernel == "k_demand" and ppl > 1:
+        return f"k_demand_multi<{ppl}>"
+    return kernel
 
 
 def b_iter_shares(inst):
@@ -215,6 +226,8 @@ def large_run(args, torch, te, W, dev, with_oracle=True):
     prob.solve(o64, stats=False)
     torch.cuda.synchronize()
     ms_iter = (time.perf_counter() - t1) * 1e3 / 64
+    for nm in names:  # counters of the same kernels (summary committed under profiles/), if current
+        kr[nm]["traffic"] = measured_traffic(profiled_name(nm, st64["paths_per_lane"]), TRAFFIC_FILE_LARGE)
     err = None
     if with_oracle:
         import oracle as O
@@ -367,10 +380,11 @@ def main():
     # ---- per-kernel device time (HIP events attached to each dispatch) and roofline ----
     ms_dem, ms_link = prob.kernel_times(te.Options(**gopt), iters=min(K_star, 1024))
     info = prob.info()
+    info_ppl = run(1, project=False)[2]["paths_per_lane"]
     names, kr, it = roofline_of(inst, info, ms_dem, ms_link)
     dom = names[0] if ms_dem >= ms_link else names[1]
     roofline = {"bound": "hbm", "achieved": kr[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kr[dom]["frac"], "traffic": measured_traffic(dom), "kernel": dom,
+                "frac": kr[dom]["frac"], "traffic": measured_traffic(profiled_name(dom, info_ppl)), "kernel": dom,
                 "bytes_per_launch": kr[dom]["algorithmic_bytes"], "avg_launch_us": kr[dom]["avg_launch_us"],
                 "bytes_basis": "algorithmic bytes of the kernel's steps: demand step 4 nnz + 4 (P+1) + 16 P + 16 D, "
                                "link step 40 E (int32 indices, FP32 state, FP64 loads)",
