@@ -96,7 +96,10 @@ typedef struct {
   int32_t alpha_max;   /* largest alpha an increment may reach (flag TE_HIT_ALPHA_MAX); default 64 */
   int32_t fixed_iters; /* > 0: run exactly this many iterations, no stop test; alpha and beta still adapt */
   int32_t adapt_beta;  /* 0: keep beta = beta0 */
-  int32_t beta_every;  /* apply the residual-balancing rule after every beta_every-th iteration; default 5 */
+  int32_t beta_every;  /* the residual-balancing rule may act only after every beta_every-th iteration;
+                          default 1 (every iteration, section 3.4).  After the n-th reversal of beta's
+                          direction the rule rests for the next 2^n - 1 iterations (2^20 at most), so
+                          it cannot cycle; the per-link rule acts on the same iterations */
   int32_t project;     /* 1: run the feasibility projection of Algorithm 2 before returning (default) */
   int32_t engine;      /* TE_ENGINE_* */
   int32_t record;      /* 1: keep the (beta, alpha) schedule and checkpoints for te_grad */

@@ -53,7 +53,8 @@ class _Options(ctypes.Structure):
 class _Warm(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("S", ctypes.c_void_p), ("y", ctypes.c_void_p), ("ucon", ctypes.c_void_p),
                 ("ucap", ctypes.c_void_p), ("udem", ctypes.c_void_p), ("uneg", ctypes.c_void_p),
-                ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("w", ctypes.c_void_p)]
+                ("beta", ctypes.c_double), ("alpha", ctypes.c_double), ("w", ctypes.c_void_p),
+                ("last_dir", ctypes.c_int32), ("n_rev", ctypes.c_int32), ("rule_rest", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -61,7 +62,8 @@ class _Stats(ctypes.Structure):
                 ("final_alpha", ctypes.c_double), ("beta", ctypes.c_double), ("r", ctypes.c_double),
                 ("s", ctypes.c_double), ("max_cap_viol_rel", ctypes.c_double),
                 ("max_dem_viol_rel", ctypes.c_double), ("collapse_dev", ctypes.c_double),
-                ("root_steps_mean", ctypes.c_double), ("root_steps_max", ctypes.c_int32)]
+                ("root_steps_mean", ctypes.c_double), ("root_steps_max", ctypes.c_int32),
+                ("last_dir", ctypes.c_int32), ("n_rev", ctypes.c_int32), ("rule_rest", ctypes.c_int32)]
 
 
 class _State(ctypes.Structure):
@@ -116,7 +118,7 @@ class Options:
     sched_alpha: np.ndarray | None = None
     root_max_steps: int = 200
     dual_res_scaled: bool = False
-    beta_every: int = 5
+    beta_every: int = 1
     per_link: bool = False   # per-link penalties beta * w_e, w_e adapted per link
     w_min: float = 0.25      # bounds on w_e (wider bounds let the rule starve a link's penalty: with
     w_max: float = 4.0       # [1e-2, 1e2] a 7-node instance stalled at alpha = 0)
@@ -148,6 +150,7 @@ class Result:
     dual_con: np.ndarray
     y: np.ndarray
     w: np.ndarray            # [E] per-link penalty factors at the end (ones without per_link)
+    backoff: tuple = (0, 0, 0)  # balancing rule: last direction, reversals, sweeps still at rest
 
     @property
     def schedule(self):
@@ -161,7 +164,7 @@ class Result:
         s = self.scale
         return dict(x=self.x_raw * s, S=self.S_raw * s, y=self.y * s, ucon=self.dual_con * s,
                     ucap=self.dual_cap * s, udem=self.dual_dem * s, uneg=self.dual_neg * s,
-                    beta=self.beta, alpha=self.final_alpha, w=self.w.copy())
+                    beta=self.beta, alpha=self.final_alpha, w=self.w.copy(), backoff=self.backoff)
 
 
 def _p(a):
@@ -236,6 +239,7 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
             setattr(w, name, a.ctypes.data)
         w.beta = float(warm["beta"])
         w.alpha = float(warm["alpha"])
+        w.last_dir, w.n_rev, w.rule_rest = (int(v) for v in warm.get("backoff", (0, 0, 0)))
         if warm.get("w") is not None:
             wa = np.ascontiguousarray(warm["w"], np.float64)
             if wa.shape != (E,):
@@ -257,7 +261,7 @@ def solve(inst, opts: Options | None = None, x0=None, want_state: bool = True, w
                   collapse_dev=stats.collapse_dev, root_steps_mean=stats.root_steps_mean,
                   root_steps_max=stats.root_steps_max, trace=trace[:it].copy(), dual_dem=dd, dual_cap=dc,
                   dual_neg=dn, dual_con=None if dcon is None else dcon[:nnz], y=None if yy is None else yy[:nnz],
-                  w=w_out)
+                  w=w_out, backoff=(stats.last_dir, stats.n_rev, stats.rule_rest))
 
 
 def threads(n: int = 0) -> int:

@@ -35,6 +35,9 @@
  *        (section 3.4, dual and primal residual).
  *     5. adaptive beta by residual balancing (section 3.4, A = 10, C = 2
  *        from section 3.6); scaled duals are divided by the same factor.
+ *        READING: applied after every sweep, as the paper states, except
+ *        that after the n-th reversal of beta's direction the rule rests for
+ *        the next 2^n - 1 sweeps (on instances where it cycles).
  *     6. alpha-increments and the stagnation stop (section 3.4,
  *        Algorithm 1).
  *   After the loop, the feasibility projection of Algorithm 2 (section 3.5).
@@ -91,6 +94,7 @@ typedef struct {
   double alpha;        /* fairness reached (capped at alpha_target) */
   const double *w;     /* nullable [E]: per-link penalty factors (per_link); the link duals are scaled
                           for beta * w_e */
+  int32_t last_dir, n_rev, rule_rest; /* back-off of the balancing rule (go_stats) */
 } go_warm;
 
 typedef struct {
@@ -110,7 +114,7 @@ typedef struct {
   int32_t sched_len;
   int32_t root_max_steps;    /* Newton-bisection step cap (default 200) */
   int32_t dual_res_scaled;   /* 1: s = beta * ||x^{k+1} - x^k||, 0: as printed, without beta */
-  int32_t beta_every;        /* apply the residual-balancing rule after every T-th sweep (READING) */
+  int32_t beta_every;        /* rule cadence: only after every T-th sweep (1 = every sweep, READING) */
   const go_warm *warm;       /* nullable: continue from this state instead of initialising */
   int32_t per_link;          /* 1: per-link penalties beta * w_e, w_e adapted per link (READING) */
   double w_min, w_max;       /* bounds on w_e */
@@ -123,6 +127,9 @@ typedef struct {
   double collapse_dev;                       /* max |dual_con_{e,r} - dual_cap_e| over all sweeps */
   double root_steps_mean;
   int32_t root_steps_max;
+  /* back-off of the balancing rule at the end: direction of its last change of beta, reversals so
+     far, sweeps it still rests */
+  int32_t last_dir, n_rev, rule_rest;
 } go_stats;
 
 /* Optional state read-back (all nullable, normalised units). */
@@ -527,6 +534,10 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   }
   int j = 0, k = 0, stop = 0;
   double r_res = 0.0, s_res = 0.0;
+  /* back-off of the residual-balancing rule: direction of its last change of beta (+1, -1, 0 for
+     none yet), number of reversals of that direction, and the first sweep count at which it may act
+     again */
+  int last_dir = wm ? wm->last_dir : 0, n_rev = wm ? wm->n_rev : 0, rule_from = wm ? wm->rule_rest : 0;
   long long steps_total = 0;
   int steps_max = 0;
 
@@ -658,15 +669,27 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
       st->trace[5 * k + 4] = stats->flags;
     }
 
-    /* 5. adaptive beta (residual balancing) and rescale of the scaled duals */
+    /* 5. adaptive beta (residual balancing) and rescale of the scaled duals.  READING: the rule
+       may act after sweep k + 1 when the cadence admits it and its back-off has run out; a change
+       of beta opposite to the previous one is the n-th reversal and makes the rule rest for the
+       next 2^n - 1 sweeps (2^20 at most) */
     double f = 1.0;
+    const int rule_now = ((k + 1) % (opt->beta_every > 0 ? opt->beta_every : 1)) == 0 && k + 1 >= rule_from;
     if (replay) {
       if (k + 1 < opt->sched_len) f = opt->sched_beta[k + 1] / opt->sched_beta[k];
-    } else if (opt->adapt_beta && ((k + 1) % (opt->beta_every > 0 ? opt->beta_every : 1)) == 0) {
+    } else if (opt->adapt_beta && rule_now) {
       if (r_res > opt->A * s_res) {
         if (beta * opt->C <= opt->beta_max) f = opt->C; else stats->flags |= GO_HIT_BETA_BOUND;
       } else if (s_res > opt->A * r_res) {
         if (beta / opt->C >= opt->beta_min) f = 1.0 / opt->C; else stats->flags |= GO_HIT_BETA_BOUND;
+      }
+      if (f != 1.0) {
+        const int dir = f > 1.0 ? 1 : -1;
+        if (last_dir != 0 && dir != last_dir) {
+          ++n_rev;
+          rule_from = k + 1 + (1 << (n_rev < 20 ? n_rev : 20));
+        }
+        last_dir = dir;
       }
     }
     if (f != 1.0) {
@@ -680,8 +703,9 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
        link e on its own residuals -- r_e = the change of link e's scaled duals (its capacity dual
        and the consensus duals of its paths; each equals that constraint's residual), s_e = the
        change of the rates of the paths through e -- moves w_e by C within [w_min, w_max] and divides
-       link e's scaled duals by the same factor */
-    if (opt->per_link && ((k + 1) % (opt->beta_every > 0 ? opt->beta_every : 1)) == 0) {
+       link e's scaled duals by the same factor; it acts on the sweeps where the global rule may
+       act (the same cadence and back-off) */
+    if (opt->per_link && rule_now) {
       for (int e = 0; e < E; ++e) {
         if (lptr[e + 1] == lptr[e]) continue;
         double s2 = 0.0;
@@ -735,6 +759,9 @@ int gate_oracle_solve(int n_links, const double *capacity, int n_paths, const in
   stats->s = s_res;
   stats->root_steps_mean = (k > 0 && D > 0) ? (double)steps_total / ((double)k * D) : 0.0;
   stats->root_steps_max = steps_max;
+  stats->last_dir = last_dir;
+  stats->n_rev = n_rev;
+  stats->rule_rest = rule_from > k ? rule_from - k : 0;
 
   /* violations before projection */
   {

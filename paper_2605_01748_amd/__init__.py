@@ -129,7 +129,7 @@ class Options:
     alpha_max: int = 64
     fixed_iters: int = 0
     adapt_beta: bool = True
-    beta_every: int = 5
+    beta_every: int = 1
     project: bool = True
     engine: int = ENGINE_AUTO
     record: bool = False

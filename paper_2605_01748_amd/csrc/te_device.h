@@ -271,7 +271,14 @@ __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *e
 // ------------------------------------------------------------------------------------------
 // Control decision after iteration k (sections 3.4): residual balancing of beta with
 // rescale of the scaled duals, alpha-increments, stop test.  Sums: [s2, r2, cap, dem].
+// The balancing rule may act after iteration k when the cadence admits k + 1 and the back-off
+// has run out: a change of beta opposite to the previous one is the n-th reversal and rests the
+// rule for the next 2^n - 1 iterations (2^20 at most).
 // ------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool rule_may_act(const Params &prm, const Ctrl &c) {
+  return ((c.k + 1) % prm.beta_every) == 0 && c.k + 1 >= c.rule_from;
+}
+
 __device__ inline Ctrl decide(const Ctrl &prev, const double *sums, const Params &prm) {
 #pragma clang fp contract(off)
   if (!prev.pending) return prev;
@@ -292,11 +299,19 @@ __device__ inline Ctrl decide(const Ctrl &prev, const double *sums, const Params
     c.beta = nb;
     c.alpha = prm.sched_alpha[kk];
   } else {
-    if (prm.adapt_beta && (kdone % prm.beta_every) == 0) {
+    if (prm.adapt_beta && rule_may_act(prm, prev)) {
       if (r > prm.A * s) {
         if (prev.beta * prm.C <= prm.beta_max) f = prm.C; else c.flags |= F_BETA_BOUND;
       } else if (s > prm.A * r) {
         if (prev.beta / prm.C >= prm.beta_min) f = 1.0 / prm.C; else c.flags |= F_BETA_BOUND;
+      }
+      if (f != 1.0) {
+        const int dir = f > 1.0 ? 1 : -1;
+        if (prev.last_dir != 0 && dir != prev.last_dir) {
+          c.n_rev = prev.n_rev + 1;
+          c.rule_from = kdone + (1 << (c.n_rev < 20 ? c.n_rev : 20));
+        }
+        c.last_dir = dir;
       }
     }
     c.beta = prev.beta * f;
@@ -347,6 +362,9 @@ __device__ inline Ctrl initial_ctrl(const Params &prm) {
   c.flags = 0;
   c.stop_iter = -1;
   c.pending = 0;
+  c.last_dir = 0;
+  c.n_rev = 0;
+  c.rule_from = 0;
   return c;
 }
 

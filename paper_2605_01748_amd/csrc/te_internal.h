@@ -24,6 +24,9 @@ struct Ctrl {
   int32_t flags;      // TE_* flags
   int32_t stop_iter;  // first iteration whose stop test passed (-1 none)
   int32_t pending;
+  int32_t last_dir;   // direction of the rule's last change of beta: +1, -1, 0 (none yet)
+  int32_t n_rev;      // reversals of that direction so far
+  int32_t rule_from;  // the rule rests until iteration count rule_from (back-off after a reversal)
 };
 
 // Constant parameters of one solve.

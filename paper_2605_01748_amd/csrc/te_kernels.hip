@@ -180,7 +180,8 @@ __global__ void k_init(Prob p, State s, const Params *prmp, const float *x0, dou
 
 // Continuation from the state of the previous solve (warm restart): rate-like state converted to
 // the current units (rescale = old scale / new scale), the control record restarted at iteration 0
-// with the previous beta and alpha (alpha capped at the target; a replayed schedule overrides both).
+// with the previous beta and alpha (alpha capped at the target; a replayed schedule overrides both)
+// and the balancing rule's back-off where it stood (the rest still due counts from iteration 0).
 // The scaled duals in memory are still at the penalty of the last iteration run (the rescale that
 // the final decision took is applied lazily by the next iteration), so the first iteration divides
 // them by beta_new / beta_last, like any other change of beta.
@@ -208,6 +209,9 @@ __global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
     if (prm.sched_beta == nullptr) {
       c.beta = fin.beta;
       c.alpha = fmin(fin.alpha, prm.alpha_target);
+      c.last_dir = fin.last_dir;
+      c.n_rev = fin.n_rev;
+      c.rule_from = fin.rule_from > fin.k ? fin.rule_from - fin.k : 0;
     }
     c.inv_f = fin.beta * fin.inv_f / c.beta;  // penalty of the stored duals over the new one
     s.ctrl[0] = c;
@@ -286,9 +290,10 @@ __device__ __forceinline__ void gather_path_w(const Prob &p, const State &s, int
   }
 }
 
-// the per-link rule acts after this iteration (the same cadence as the residual-balancing rule)
+// the per-link rule acts after this iteration (the iterations where the residual-balancing rule
+// may act: the same cadence and back-off)
 __device__ __forceinline__ bool per_link_rule_now(const Params &prm, const Ctrl &cs) {
-  return prm.per_link && ((cs.k + 1) % prm.beta_every) == 0;
+  return prm.per_link && rule_may_act(prm, cs);
 }
 
 __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const Params *prmp, int par) {

@@ -197,7 +197,7 @@ void te_default_options(te_options *o) {
   o->alpha_max = 64;
   o->fixed_iters = 0;
   o->adapt_beta = 1;
-  o->beta_every = 5;
+  o->beta_every = 1;
   o->project = 1;
   o->engine = TE_ENGINE_AUTO;
   o->record = 0;

@@ -21,7 +21,15 @@ SCORE_TOL = 4e-6  # relative resolution of the GPU's FP32 log-score, with margin
 def ambiguous_paths(inst, xm, scores, alpha):
     """Boolean mask of paths whose link-phase order is not decided at FP32 resolution.
     xm: rates after the demand phase; scores: the oracle's FP64 log-scores of the link phase (at
-    alpha = 0 they depend on the violated-link count alone)."""
+    alpha = 0 they depend on the violated-link count alone).
+
+    On each violated link the entries sorted by FP64 score fall into clusters: maximal runs in
+    which each neighbour is within the FP32 resolution of the next.  Entries with the same score
+    inputs (violated-link count and, for alpha > 0, demand sum) get equal scores on both sides and
+    keep their path-index order; entries with different inputs may be reordered within their
+    cluster, which can move one across a whole group of equal entries and change the rates above
+    every member.  So every member of a cluster that holds more than one class of inputs is
+    ambiguous."""
     P = inst.n_paths
     L = O.link_loads(inst, xm)
     viol = L > inst.capacity
@@ -43,12 +51,16 @@ def ambiguous_paths(inst, xm, scores, alpha):
     fin = np.isfinite(sc[1:]) & np.isfinite(sc[:-1])
     with np.errstate(invalid="ignore"):
         close = np.abs(sc[1:] - sc[:-1]) <= SCORE_TOL * np.maximum(1.0, np.maximum(np.abs(sc[1:]), np.abs(sc[:-1])))
-    a, b = pi[:-1], pi[1:]
-    # same key inputs: both sides compute equal scores and break the tie by path index
-    identical = (cp[a] == cp[b]) & ((S[dem_of[a]] == S[dem_of[b]]) | (alpha == 0.0))
-    hit = same & fin & close & ~identical
-    amb[a[hit]] = True
-    amb[b[hit]] = True
+    link_ = same & fin & close
+    cluster = np.concatenate([[0], np.cumsum(~link_)])  # entries i, i + 1 share a cluster iff link_[i]
+    # class of an entry's score inputs
+    cls_S = S[dem_of[pi]] if alpha != 0.0 else np.zeros(pi.size)
+    _, cls = np.unique(np.stack([cp[pi].astype(np.float64), cls_S]), axis=1, return_inverse=True)
+    cls = np.asarray(cls).ravel()
+    # clusters holding more than one class
+    pairs = np.unique(np.stack([cluster, cls]), axis=1)
+    n_cls = np.bincount(pairs[0], minlength=cluster.max() + 1)
+    amb[pi[n_cls[cluster] > 1]] = True
     return amb
 
 

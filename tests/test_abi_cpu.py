@@ -27,7 +27,7 @@ def test_exports_every_declared_symbol():
 def test_default_options_match_header_defaults():
     o, _ = te.Options().to_c()
     assert np.isinf(o.alpha_target) and o.gamma == 1e-3 and o.beta0 == 1.0
-    assert o.A == 10.0 and o.C == 2.0 and o.beta_every == 5 and o.project == 1 and o.ckpt_every == 16
+    assert o.A == 10.0 and o.C == 2.0 and o.beta_every == 1 and o.project == 1 and o.ckpt_every == 16
 
 
 def _inst():

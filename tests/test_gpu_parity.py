@@ -607,13 +607,15 @@ def _first_divergence(gb, ga, ob, oa):
 
 
 @pytest.mark.parametrize("name,engine,K", [("waxman20", "block", 833), ("waxman20", "graph", 833),
-                                           ("waxman150", "graph", 833)])
+                                           ("waxman150", "graph", 833), ("parking2", "block", 400),
+                                           ("parking2", "graph", 400), ("parking3", "graph", 400)])
 def test_adaptive_control_matches_oracle_trace(te, c1, c2, name, engine, K):
     """The GPU's own control (no replay): its sequence of (beta_k, alpha_k) equals the oracle's, and its
     residuals r_k, s_k (section 3.4) agree with the oracle's to 1e-6 relative, over K iterations of
     the max-min solve.  The schedules may only part where the oracle's decision was a near-tie
-    (r within 1e-6 of A s or s of A r, or a residual within 1e-6 of gamma)."""
-    inst = c1 if name == "waxman20" else c2
+    (r within 1e-6 of A s or s of A r, or a residual within 1e-6 of gamma).  On the parking lots the
+    balancing rule reverses six times in 400 iterations, so its back-off is exercised."""
+    inst = {"waxman20": c1, "waxman150": c2}.get(name) or W.parking_lot(int(name[-1]))
     r = O.solve(inst, O.Options(fixed_iters=K, project=False), want_state=False)
     ot = r.trace
     prob = te.Problem(inst)

@@ -129,9 +129,10 @@ def test_per_link_full_matches_collapsed(waxman20):
 
 
 def test_per_link_rescale_keeps_unscaled_multipliers(waxman20):
-    """The rule first acts after sweep 5: with it, every link's w_e * u_cap_e after that sweep equals
-    u_cap_e of the same 5 sweeps with the factors pinned at 1 (w in [1, 1]); rates are untouched."""
-    base = dict(fixed_iters=5, project=False, per_link=True, adapt_beta=False)
+    """With the cadence 5 the rule first acts after sweep 5: with it, every link's w_e * u_cap_e after
+    that sweep equals u_cap_e of the same 5 sweeps with the factors pinned at 1 (w in [1, 1]); rates
+    are untouched."""
+    base = dict(fixed_iters=5, project=False, per_link=True, adapt_beta=False, beta_every=5)
     a = O.solve(waxman20, O.Options(**base))
     b = O.solve(waxman20, O.Options(w_min=1.0, w_max=1.0, **base))
     assert np.any(a.w != 1.0) and np.all(b.w == 1.0)

@@ -12,6 +12,9 @@ formulas) or against invariants that any correct implementation satisfies.
   the first sweep after the first increment.
 * Warm state (Algorithm 1's optional inputs): continuing a solve from its own state reproduces the
   uninterrupted run, including a penalty change at the seam and a change of units.
+* Residual balancing with back-off: the beta sequence of a run on which the rule reverses is the
+  rule's output for the residuals recorded, and the run converges where the rule without rests
+  cycles; the back-off crosses a warm seam.
 * Algorithm 2's score in FP64: scores closer than single precision resolves are still ordered.
 """
 import math
@@ -159,18 +162,17 @@ def test_warm_continuation_replayed(collapsed):
 
 
 def test_warm_continuation_adaptive():
-    """Adaptive beta and alpha: 130 sweeps then 100 warm sweeps (the residual-balancing cadence
-    aligned at the seam, a beta change decided after sweep 130, an alpha increment after 150) follow
-    the uninterrupted 230-sweep run, schedule included."""
+    """Adaptive beta and alpha: 128 sweeps then 102 warm sweeps (a beta change decided after sweep
+    128, an alpha increment after 131) follow the uninterrupted 230-sweep run, schedule included."""
     inst = W.waxman20(0)
     o = dict(project=False, gamma=3e-2)
     full = O.solve(inst, O.Options(fixed_iters=230, **o))
-    first = O.solve(inst, O.Options(fixed_iters=130, **o))
-    second = O.solve(inst, O.Options(fixed_iters=100, **o), warm=first.warm_state())
+    first = O.solve(inst, O.Options(fixed_iters=128, **o))
+    second = O.solve(inst, O.Options(fixed_iters=102, **o), warm=first.warm_state())
     b, a = full.trace[:, 1], full.trace[:, 0]
-    assert b[130] != b[129] and a[151] != a[150]
-    np.testing.assert_array_equal(second.trace[:, 1], b[130:])
-    np.testing.assert_array_equal(second.trace[:, 0], a[130:])
+    assert b[128] != b[127] and a[131] != a[130]
+    np.testing.assert_array_equal(second.trace[:, 1], b[128:])
+    np.testing.assert_array_equal(second.trace[:, 0], a[128:])
     np.testing.assert_allclose(second.x_raw, full.x_raw, rtol=0, atol=1e-11)
 
 
@@ -227,3 +229,60 @@ def test_projection_stages():
     on = Cp > 0
     np.testing.assert_allclose(sc[on], 2.0 * np.log(S[on]) + np.log(Cp[on]), rtol=1e-15, atol=1e-15)
     assert np.all(np.isneginf(sc[~on]))
+
+
+# ------------------------------------------------------------------------------------------
+# Residual balancing with back-off.  The 2-link parking lot at alpha = 1 is an instance on which
+# the rule applied after every sweep keeps beta cycling between two values and the iterate never
+# settles; with the back-off (after the n-th reversal of beta's direction the rule rests for the
+# next 2^n - 1 sweeps) it converges to the alpha-fair optimum (closed form in test_oracle_pins).
+# ------------------------------------------------------------------------------------------
+def _expected_betas(tr, beta0, A=10.0, C=2.0, every=1):
+    """The beta of every sweep from the residuals the trace recorded, by the rule as defined: after
+    sweep k (1-based count k + 1), if the cadence admits it and no rest is due, multiply by C when
+    r > A s, divide by C when s > A r; a change against the previous direction is a reversal."""
+    betas = [beta0]
+    last, nrev, rest_until = 0, 0, 0
+    for k in range(len(tr) - 1):
+        b, r, s = betas[-1], tr[k, 2], tr[k, 3]
+        d = 0
+        if (k + 1) % every == 0 and k + 1 >= rest_until:
+            d = 1 if r > A * s else (-1 if s > A * r else 0)
+        if d != 0:
+            if last != 0 and d != last:
+                nrev += 1
+                rest_until = k + 1 + 2 ** nrev
+            last = d
+        betas.append(b * C ** d)
+    return np.array(betas)
+
+
+def test_backoff_schedule_follows_the_rule():
+    inst = W.parking_lot(2)
+    r = O.solve(inst, O.Options(alpha_target=1.0, gamma=1e-10, max_iters=300000, project=False))
+    tr = r.trace
+    np.testing.assert_array_equal(tr[:, 1], _expected_betas(tr, 1.0))
+    b = tr[:, 1]
+    d = np.sign(np.diff(b))
+    d = d[d != 0]
+    assert np.count_nonzero(d[1:] != d[:-1]) >= 3      # the rule did reverse, several times
+    # a rest was taken: some sweep had r > A s or s > A r while beta stayed
+    ratio_hit = (tr[:-1, 2] > 10 * tr[:-1, 3]) | (tr[:-1, 3] > 10 * tr[:-1, 2])
+    assert np.any(ratio_hit & (b[1:] == b[:-1]))
+    assert r.flags & O.CONVERGED and r.final_alpha == 1.0
+
+
+def test_backoff_cadence_and_warm_seam():
+    """The cadence composes with the back-off, and a warm continuation carries the back-off: K1 + (400 -
+    K1) sweeps equal 400 uninterrupted ones on the 2-link parking lot, the seam inside a rest after
+    several reversals (K1 a multiple of the cadence, which counts from the start of each solve)."""
+    inst = W.parking_lot(2)
+    o = dict(alpha_target=1.0, gamma=1e-10, project=False)
+    for every, K1 in ((1, 160), (3, 159)):
+        full = O.solve(inst, O.Options(fixed_iters=400, beta_every=every, **o))
+        np.testing.assert_array_equal(full.trace[:, 1], _expected_betas(full.trace, 1.0, every=every))
+        first = O.solve(inst, O.Options(fixed_iters=K1, beta_every=every, **o))
+        assert first.backoff[1] >= 3 and first.backoff[2] > 0
+        second = O.solve(inst, O.Options(fixed_iters=400 - K1, beta_every=every, **o), warm=first.warm_state())
+        np.testing.assert_array_equal(second.trace[:, 1], full.trace[K1:, 1])
+        np.testing.assert_allclose(second.x_raw, full.x_raw, rtol=0, atol=1e-12)

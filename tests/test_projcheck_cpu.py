@@ -30,6 +30,19 @@ def test_near_tie_marked_and_clear_order_not():
     assert not ambiguous_paths(inst, xm3, sc3, 0.0).any()
 
 
+def test_near_tie_next_to_a_tie_group_marks_the_group():
+    # paths 0 and 1 have identical key inputs (equal sums), path 2 is a near-tie of both: FP32 may put
+    # path 2 above or below the whole group, which changes the rate above each member of the group
+    # (the 2-path group alone would keep its index order on both sides)
+    inst, x = _one_link([0.5, 0.5, 0.5 * (1 + 1e-9), 0.2])
+    _, xm, sc = O.project(inst, x, 1.0, stages=True)
+    assert ambiguous_paths(inst, xm, sc, 1.0).tolist() == [True, True, True, False]
+    # the same near-tie, its partner clearly apart from the group: only the near-tie pair is marked
+    inst2, x2 = _one_link([0.5, 0.4, 0.5 * (1 + 1e-9), 0.2])
+    _, xm2, sc2 = O.project(inst2, x2, 1.0, stages=True)
+    assert ambiguous_paths(inst2, xm2, sc2, 1.0).tolist() == [True, False, True, False]
+
+
 def test_check_projection_accepts_the_oracle_and_rejects_a_wrong_trim():
     inst, x = _one_link([0.6, 0.5, 0.2])
     ref = O.project(inst, x, 1.0)
