@@ -223,70 +223,149 @@ __global__ void k_warm(Prob p, State s, const Params *prmp, double rescale) {
 // ------------------------------------------------------------------------------------------
 // Step a1 + a2: gather along paths, per-demand Newton-bisection, rate and dual updates.
 // ------------------------------------------------------------------------------------------
-// Sums of g and q over path r's links, and its hop count.  With hop records (H > 0) the link ids
-// come from the path's fixed-width record (16-bit ids in path order, 0xffff past the end), whose
-// loads depend on r only; all (g, q) pairs are then gathered together.  Otherwise from the CSR
-// layout, eight link ids, then their pairs, at a time.
-__device__ __forceinline__ void gather_path(const Prob &p, const State &s, int r, double &sg, double &sq, int &n) {
-  sg = 0.0;
-  sq = 0.0;
-  if (p.H > 0) {
-    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
-    uint2 w[kMaxHopSlots / 4];
+// Gathers of the (g, q) pairs along paths.  The kernels' time goes into dependent memory latency, so
+// every load of a round is issued unconditionally and in one straight-line block: a padding slot, a
+// slot past the path's end or a lane without a path reads a valid entry (g, q of link 0, a repeated
+// record word) and is masked out of the sums.  A load inside a divergent branch is waited for before
+// the branch rejoins, which would serialise the hops of a path into one round trip each.  The sums
+// are taken in hop order, a masked slot adding 0 (so they equal a plain loop's up to the sign of a
+// zero sum).
+
+// id of slot k of a fixed-width hop record (16-bit link ids in path order, 0xffff past the end)
+__device__ __forceinline__ unsigned hop_id(const uint2 (&w)[kMaxHopSlots / 4], int k) {
+  const uint2 q = w[k >> 2];
+  const unsigned h = (k & 2) ? q.y : q.x;
+  return (k & 1) ? (h >> 16) : (h & 0xffffu);
+}
+
+// the record of path r; words past the record's H slots read as padding (their load reads word 0)
+__device__ __forceinline__ void load_record(const Prob &p, int r, uint2 (&w)[kMaxHopSlots / 4]) {
+  const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
 #pragma unroll
-    for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
-    n = 0;
-#pragma unroll
-    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
-      const unsigned id[4] = {w[q].x & 0xffffu, w[q].x >> 16, w[q].y & 0xffffu, w[q].y >> 16};
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (id[u] != 0xffffu) {
-          const double2 v = s.gq[id[u]];
-          sg += v.x;
-          sq += v.y;
-          ++n;
-        }
-    }
-  } else {
-    const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
-    n = i1 - i0;
-    for (int ib = i0; ib < i1; ib += 8) {
-      int e[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
-#pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (e[u] >= 0) {
-          const double2 v = s.gq[e[u]];
-          sg += v.x;
-          sq += v.y;
-        }
-    }
+  for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+    const bool in = 4 * q < p.H;
+    const uint2 v = rec[in ? q : 0];
+    w[q] = in ? v : make_uint2(~0u, ~0u);
   }
 }
 
-// The same with per-link penalty factors: sums of w_e g_e and w_e q_e over path r's links, and
-// W_r = sum of w_e (the path's weight in the rate update, n_r when every w_e is 1).
-__device__ __forceinline__ void gather_path_w(const Prob &p, const State &s, int r, double &sg, double &sq,
-                                              double &Wr) {
-  sg = 0.0;
-  sq = 0.0;
-  Wr = 0.0;
-  const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
-  for (int ib = i0; ib < i1; ib += 8) {
-    int e[8];
+// hop count of a record (its ids; padding only at the end).  Computed from every word, so that the
+// record's loads are all waited for at once rather than split around the first use.
+__device__ __forceinline__ int record_hops(const uint2 (&w)[kMaxHopSlots / 4]) {
+  int n = 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
+  for (int k = 0; k < kMaxHopSlots; ++k) n += hop_id(w, k) != 0xffffu ? 1 : 0;
+  return n;
+}
+
+// Sums of g and q, and hop counts, over the NP paths of a lane whose records are w[j] (path j taken
+// where bit j of on is set), in rounds of R slots: a round issues the R * NP loads together and runs
+// only while some lane of the wavefront has a hop in it.
+template <int NP, int R>
+__device__ __forceinline__ void gather_records(const State &s, const uint2 (&w)[NP][kMaxHopSlots / 4], unsigned on,
+                                               double (&sg)[NP], double (&sq)[NP], int (&n)[NP]) {
+  int nmax = 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (e[u] >= 0) {
-        const double2 v = s.gq[e[u]];
-        const double we = s.w[e[u]];
-        sg += we * v.x;
-        sq += we * v.y;
-        Wr += we;
+  for (int j = 0; j < NP; ++j) {
+    sg[j] = 0.0;
+    sq[j] = 0.0;
+    n[j] = ((on >> j) & 1u) ? record_hops(w[j]) : 0;
+    nmax = max(nmax, n[j]);
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < kMaxHopSlots; k0 += R) {
+    if (!__any(nmax > k0)) break;
+    unsigned id[NP][R];
+    double2 v[NP][R];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < R; ++u) id[j][u] = k0 + u < n[j] ? hop_id(w[j], k0 + u) : 0u;
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < R; ++u) v[j][u] = s.gq[id[j][u]];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const double m = k0 + u < n[j] ? 1.0 : 0.0;  // a product, not a select: a select of a
+        sg[j] = fma(v[j][u].x, m, sg[j]);             // loaded value is turned into a branch
+        sq[j] = fma(v[j][u].y, m, sq[j]);             // around the load
       }
+  }
+}
+
+// The same from the CSR layout (no hop records: a path with more than kMaxHopSlots hops, or a link id
+// that does not fit 16 bits), eight hops of each path a round.  With per-link penalties (WEIGHTED)
+// the sums are of w_e g_e and w_e q_e, and Wr[j] = sum of w_e (the path's weight in the rate update);
+// otherwise Wr[j] is the hop count.  Every path has at least one link, so its first entry is a valid
+// stand-in for a slot past its end.
+template <int NP, bool WEIGHTED>
+__device__ __forceinline__ void gather_csr(const Prob &p, const State &s, const int (&r)[NP], unsigned on,
+                                           double (&sg)[NP], double (&sq)[NP], double (&Wr)[NP]) {
+  int i0[NP], len[NP];
+  int lmax = 0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    i0[j] = p.pptr[r[j]];
+    len[j] = ((on >> j) & 1u) ? p.pptr[r[j] + 1] - i0[j] : 0;
+    lmax = max(lmax, len[j]);
+    sg[j] = 0.0;
+    sq[j] = 0.0;
+    Wr[j] = 0.0;
+  }
+  for (int k0 = 0; __any(k0 < lmax); k0 += 8) {
+    int e[NP][8];
+    double2 v[NP][8];
+    double we[NP][8];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[j][u] = p.plinks[k0 + u < len[j] ? i0[j] + k0 + u : i0[j]];
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        v[j][u] = s.gq[e[j][u]];
+        we[j][u] = WEIGHTED ? s.w[e[j][u]] : 1.0;
+      }
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double m = k0 + u < len[j] ? 1.0 : 0.0;  // a product, not a select (see above)
+        const double wm = we[j][u] * m;
+        sg[j] = fma(WEIGHTED ? we[j][u] * v[j][u].x : v[j][u].x, m, sg[j]);
+        sq[j] = fma(WEIGHTED ? we[j][u] * v[j][u].y : v[j][u].y, m, sq[j]);
+        Wr[j] += wm;
+      }
+  }
+}
+
+// Sums along the NP paths r[j] of a lane (bit j of on): from the hop records where the instance has
+// them, else from the CSR layout; with per-link penalties always from the CSR layout, weighted.
+template <int NP>
+__device__ __forceinline__ void gather_paths(const Prob &p, const State &s, bool per_link, const int (&r)[NP],
+                                             unsigned on, double (&sg)[NP], double (&sq)[NP], double (&Wr)[NP]) {
+  if (per_link) {
+    gather_csr<NP, true>(p, s, r, on, sg, sq, Wr);
+  } else if (p.H > 0) {
+    // one path after the other: a path's record and its round of eight loads are then all that is
+    // live, which keeps the kernels with several paths per lane within their register budget
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      uint2 w[1][kMaxHopSlots / 4];
+      load_record(p, r[j], w[0]);
+      double g1[1], q1[1];
+      int n1[1];
+      gather_records<1, 8>(s, w, (on >> j) & 1u, g1, q1, n1);
+      sg[j] = g1[0];
+      sq[j] = q1[0];
+      Wr[j] = (double)n1[0];
+    }
+  } else {
+    gather_csr<NP, false>(p, s, r, on, sg, sq, Wr);
   }
 }
 
@@ -310,28 +389,29 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
   const int bl = xcd_chunk(blockIdx.x, gridDim.x);
   const int c = bl * (kThreads >> p.logG) + (t >> p.logG);
   // gathers (independent of the control record): sums of g and q along the path
-  int r0 = 0, np = 0, r = 0, n = 1;
+  int r0 = 0, np = 0, r = 0;
   double xr = 0.0, ung = 0.0, Dc = 0.0, Wn = 1.0;
   double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
   bool on = false;
-  if (!ctl && c < p.D) {
-    Dc = p.Dn[c];  // per-demand loads first: they depend on c only
-    udc = s.udem[c];
-    S0 = s.S[c];
-    r0 = p.dptr[c];
-    np = p.dptr[c + 1] - r0;
-    on = lane < np;
-    r = r0 + (on ? lane : 0);
-    if (on) {
-      xr = s.x[r];
-      ung = s.uneg[r];
-      if (prm.per_link) {
-        gather_path_w(p, s, r, sg, sq, Wn);
-      } else {
-        gather_path(p, s, r, sg, sq, n);
-        Wn = (double)n;
-      }
+  if (!ctl) {
+    if (c < p.D) {
+      Dc = p.Dn[c];  // per-demand loads first: they depend on c only
+      udc = s.udem[c];
+      S0 = s.S[c];
+      r0 = p.dptr[c];
+      np = p.dptr[c + 1] - r0;
     }
+    on = lane < np;
+    r = r0 + (on ? lane : 0);  // a lane without a path reads the demand's first (or path 0)
+    const double xv = s.x[r], uv = s.uneg[r];
+    xr = on ? xv : 0.0;
+    ung = on ? uv : 0.0;
+    const int rr[1] = {r};
+    double g1[1], q1[1], w1[1];
+    gather_paths<1>(p, s, prm.per_link, rr, on ? 1u : 0u, g1, q1, w1);
+    sg = g1[0];
+    sq = q1[0];
+    Wn = on ? w1[0] : 1.0;
   }
   if (ctl) finish_ctrl(cp, prm, &cs);
   __syncthreads();
@@ -405,23 +485,23 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
     S0 = s.S[c];
     r0 = p.dptr[c];
     np = p.dptr[c + 1] - r0;
+  }
+  {
+    int rr[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       const int idx = lane + j * Gp;
-      if (idx < np) {
-        const int r = r0 + idx;
-        on |= 1u << j;
-        xr[j] = s.x[r];
-        ung[j] = s.uneg[r];
-        if (prm.per_link) {
-          gather_path_w(p, s, r, sg[j], sq[j], Wn[j]);
-        } else {
-          int nj;
-          gather_path(p, s, r, sg[j], sq[j], nj);
-          Wn[j] = (double)nj;
-        }
-      }
+      const bool oj = idx < np;
+      on |= oj ? 1u << j : 0u;
+      rr[j] = r0 + (oj ? idx : 0);  // a slot without a path reads the demand's first (or path 0)
+      const double xv = s.x[rr[j]], uv = s.uneg[rr[j]];
+      xr[j] = oj ? xv : 0.0;
+      ung[j] = oj ? uv : 0.0;
     }
+    double W[PPL];
+    gather_paths<PPL>(p, s, prm.per_link, rr, on, sg, sq, W);
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) Wn[j] = ((on >> j) & 1u) ? W[j] : 1.0;
   }
   if (threadIdx.x < 64) finish_ctrl(cp, prm, &cs);
   __syncthreads();
@@ -503,15 +583,17 @@ __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0
   for (int j = ja; j < jb; j += 64 * U) {
     I v[U];
     double val[U];
+    // unconditional loads (an entry past the part reads its first one, masked below), so that the
+    // U rows' index loads, then their value loads, are in flight together
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int jj = j + 64 * u + lane;
-      v[u] = jj < jb ? lpf[jj] : (I)0;
+      v[u] = lpf[jj < jb ? jj : ja];
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int jj = j + 64 * u + lane;
-      val[u] = jj < jb ? (double)vals[csc_path(v[u])] : 0.0;
+      val[u] = (double)vals[csc_path(v[u])] * (jj < jb ? 1.0 : 0.0);  // a product, not a select
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -695,6 +777,49 @@ struct PathIds {
   int i0, i1;
 };
 
+// Gathers of the scatter kernel: the loads of a path's hops inside the branches of a plain loop,
+// which the compiler waits for one at a time.  The straight-line gathers above (several loads in
+// flight) made this kernel spill: at 1,024 threads it has 128 registers a lane, and its time went up
+// (1,000-node instance, 143 -> 159 us with two paths per lane).
+__device__ __forceinline__ void gather_path_serial(const Prob &p, const State &s, int r, double &sg, double &sq, int &n) {
+  sg = 0.0;
+  sq = 0.0;
+  if (p.H > 0) {
+    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
+    uint2 w[kMaxHopSlots / 4];
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+    n = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      const unsigned id[4] = {w[q].x & 0xffffu, w[q].x >> 16, w[q].y & 0xffffu, w[q].y >> 16};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (id[u] != 0xffffu) {
+          const double2 v = s.gq[id[u]];
+          sg += v.x;
+          sq += v.y;
+          ++n;
+        }
+    }
+  } else {
+    const int i0 = p.pptr[r], i1 = p.pptr[r + 1];
+    n = i1 - i0;
+    for (int ib = i0; ib < i1; ib += 8) {
+      int e[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) e[u] = ib + u < i1 ? p.plinks[ib + u] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (e[u] >= 0) {
+          const double2 v = s.gq[e[u]];
+          sg += v.x;
+          sq += v.y;
+        }
+    }
+  }
+}
+
 __device__ __forceinline__ void gather_ids(const Prob &p, const State &s, int r, PathIds &id, double &sg,
                                            double &sq, int &n) {
   sg = 0.0;
@@ -817,7 +942,7 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
           if (KEEP)
             gather_ids(p, s, r, ids[0], sg[j], sq[j], n[j]);
           else
-            gather_path(p, s, r, sg[j], sq[j], n[j]);
+            gather_path_serial(p, s, r, sg[j], sq[j], n[j]);
         }
       }
     }
