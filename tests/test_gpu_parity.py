@@ -138,8 +138,14 @@ def test_parity_hierarchical_graph(te, c3_small, K):
     assert err.max() <= REL
 
 
+def _ragged_long():
+    # paths of up to 24 links: beyond the fixed-width hop records, so every kernel reads the CSR layout
+    return W.ragged(3, n_links=60, n_demands=50, max_hops=24)
+
+
 _EDGE = {
     "ragged0": lambda: W.ragged(0),
+    "ragged_long": _ragged_long,
     "ragged1": lambda: W.ragged(1, n_links=20, n_demands=70),
     "one_link_one_demand": lambda: W.shared_link([5.0], cap=1.0),
     "shared_link": lambda: W.shared_link([0.1, 0.5, 2.0, 8.0], cap=1.0),
@@ -151,8 +157,9 @@ _EDGE = {
 @pytest.mark.parametrize("K", [1, 64])
 @pytest.mark.parametrize("name", sorted(_EDGE))
 def test_parity_edge_cases(te, name, engine, K):
-    """Ragged path counts (1..64 per demand), paths longer than the gather batch, unused links,
-    a single link and a single demand, and the widest demand (64 paths on one link each)."""
+    """Ragged path counts (1..64 per demand), paths longer than the gather batch and than a hop
+    record, unused links, a single link and a single demand, and the widest demand (64 paths on one
+    link each)."""
     inst = _EDGE[name]()
     r, sb, sa = _oracle_run(inst, K)
     prob = te.Problem(inst)
@@ -374,12 +381,13 @@ def test_workgroup_engine_at_its_lds_limit(te):
 
 
 @pytest.mark.parametrize("ppl", [2, 4, 8])
-@pytest.mark.parametrize("name", ["waxman20", "ragged0", "waxman150"])
+@pytest.mark.parametrize("name", ["waxman20", "ragged0", "ragged_long", "waxman150"])
 def test_parity_graph_paths_per_lane(te, c1, c2, ppl, name):
     """The graph engine's demand kernel with 2, 4 and 8 paths per lane (lane groups of
     max(1, G / ppl) lanes per demand) against the oracle, schedule replayed; the handle switches
     back to one path per lane afterwards and still matches."""
-    inst = {"waxman20": c1, "waxman150": c2}.get(name) or W.ragged(0)
+    inst = {"waxman20": c1, "waxman150": c2, "ragged_long": None}.get(name) or (
+        _ragged_long() if name == "ragged_long" else W.ragged(0))
     K = 64 if name == "waxman150" else 256
     r, sb, sa = _oracle_run(inst, K)
     prob = te.Problem(inst)
@@ -724,6 +732,7 @@ _LSUM_CASES = {
     "waxman20": lambda: W.waxman20(0),
     "ragged0": lambda: W.ragged(0),
     "ragged1": lambda: W.ragged(1, n_links=20, n_demands=70),
+    "ragged_long": _ragged_long,
     "parallel_64": lambda: W.parallel_paths(np.linspace(0.5, 2.0, 64), 50.0),
     "waxman150": lambda: W.waxman150(0),
     "two_level_6": lambda: W.two_level1000(1, regions=6, backbone_links=120),
@@ -747,6 +756,7 @@ def test_parity_link_sum_variants(te, name, lsum):
                                          sched_beta=sb, sched_alpha=sa))
         info = prob.info()
         assert info["link_sums"] == ls
+        assert (info["hop_slots"] == 0) == (name == "ragged_long")
         assert (info["scatter_workgroups"] > 0) == (ls == te.LINK_SUMS_PRIVATE)
         err = _report(f"{name} link sums {ls} K={K}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
                       inst.demand)

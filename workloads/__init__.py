@@ -580,11 +580,12 @@ def parallel_paths(caps, demand) -> Instance:
     return make_instance("parallel", 2, [0] * m, [1] * m, caps, [0], [1], [demand], [[[i] for i in range(m)]])
 
 
-def ragged(seed: int = 0, n_links: int = 48, n_demands: int = 40) -> Instance:
+def ragged(seed: int = 0, n_links: int = 48, n_demands: int = 40, max_hops: int = 12) -> Instance:
     """Edge-case instance for the kernels' boundaries (not a network): demands with 1, 2, 3, 5, 8, 17,
-    33 and 64 paths (64 is the per-demand maximum), paths of 1 to 12 links (beyond the 8-hop gather
-    batch), one link on a large share of all paths, unused links with zero capacity, and demands
-    spanning four orders of magnitude.  Path link sets are drawn without repeats inside a path."""
+    33 and 64 paths (64 is the per-demand maximum), paths of 1 to max_hops links (12: beyond the 8-hop
+    gather batch; above 16: beyond the fixed-width hop records, so the kernels read the CSR layout),
+    one link on a large share of all paths, unused links with zero capacity, and demands spanning four
+    orders of magnitude.  Path link sets are drawn without repeats inside a path."""
     rng = np.random.default_rng(np.random.SeedSequence([7, seed]))
     used = n_links - 4  # the last four links carry no path
     cap = np.concatenate([rng.choice([1.0, 4.0, 10.0], size=used), np.zeros(4)])
@@ -594,7 +595,7 @@ def ragged(seed: int = 0, n_links: int = 48, n_demands: int = 40) -> Instance:
     for c in range(n_demands):
         plist = []
         for _ in range(int(counts[c])):
-            hops = int(rng.integers(1, 13))
+            hops = int(rng.integers(1, max_hops + 1))
             links = rng.choice(used - 1, size=hops, replace=False) + 1
             if rng.uniform() < 0.4:
                 links[0] = 0  # the hot link
