@@ -63,10 +63,16 @@ struct Prob {
   // per wavefront of the link kernels ([nB * kLinkWaves]): its CSC entry range [x, y) and the rank
   // (index into nzlink) of the link holding entry x, precomputed so that no wavefront searches
   const int4 *wtab;
-  // per path, its link ids as H 16-bit slots in path order, unused slots 0xffff (H a multiple of 4,
-  // at most kMaxHopSlots); H = 0 when some path has more hops or a link id does not fit 16 bits
+  // per path, its first H link ids as 16-bit slots in path order, unused slots 0xffff (H = 4 or 8);
+  // H = 0 when some path has more than kMaxHopSlots hops or a link id does not fit 16 bits.  The
+  // paths of a demand that has a path longer than H continue in overflow records of H2 slots (H2 =
+  // 4 or 8): the demand's paths hold records dovf[d], dovf[d] + 1, ... of hops2, in path order;
+  // dovf[d] = -1 for a demand whose paths all fit H (H2 = 0, hops2 and dovf null when every path does)
   const uint16_t *hops;
   int32_t H;
+  const uint16_t *hops2;
+  int32_t H2;
+  const int32_t *dovf;
   // demand kernel of the graph engine: paths per lane (1 = one lane per path) and log2 of its
   // lanes per demand, max(1, G / ppl)
   int32_t ppl, logGp;
@@ -85,6 +91,7 @@ struct Prob {
 enum { kLinkSumsPrivate = 1, kLinkSumsCsc = 2 };
 
 constexpr int kMaxHopSlots = 16;
+constexpr int kPrimarySlots = 8;  // slots of a path's primary hop record
 // graph engine: instances with at least kMultiLanes lane slots (demands x G) run the demand step
 // with min(G, kMultiPaths) paths per lane
 constexpr int64_t kMultiLanes = 1 << 20;

@@ -238,8 +238,15 @@ __device__ __forceinline__ unsigned hop_id(const uint2 (&w)[kMaxHopSlots / 4], i
   return (k & 1) ? (h >> 16) : (h & 0xffffu);
 }
 
-// the record of path r; words past the record's H slots read as padding (their load reads word 0)
-__device__ __forceinline__ void load_record(const Prob &p, int r, uint2 (&w)[kMaxHopSlots / 4]) {
+// overflow record of path r of a demand whose first path is r0 and whose dovf entry is dv (-1: the
+// demand has none)
+__device__ __forceinline__ int overflow_record(int dv, int r, int r0) { return dv >= 0 ? dv + (r - r0) : -1; }
+
+// the record of path r (its primary record, then its overflow record ovf if ovf >= 0); words past
+// them read as padding.  The loads are unconditional (a word past a record reads its word 0), so
+// that they issue together; the overflow records' loads are skipped only where the instance has
+// none (a uniform condition).
+__device__ __forceinline__ void load_record(const Prob &p, int r, int ovf, uint2 (&w)[kMaxHopSlots / 4]) {
   const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
 #pragma unroll
   for (int q = 0; q < kMaxHopSlots / 4; ++q) {
@@ -247,6 +254,24 @@ __device__ __forceinline__ void load_record(const Prob &p, int r, uint2 (&w)[kMa
     const uint2 v = rec[in ? q : 0];
     w[q] = in ? v : make_uint2(~0u, ~0u);
   }
+  if (p.H2 > 0) {
+    const uint2 *rec2 = reinterpret_cast<const uint2 *>(p.hops2 + (size_t)(ovf >= 0 ? ovf : 0) * p.H2);
+#pragma unroll
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) {
+      const int q2 = q - p.H / 4;
+      const bool in = q2 >= 0 && 4 * q2 < p.H2;
+      const uint2 v = rec2[in ? q2 : 0];
+      if (in) w[q] = ovf >= 0 ? v : make_uint2(~0u, ~0u);
+    }
+  }
+}
+
+// word q of the record of path r (primary, then overflow record ovf), padding past them
+__device__ __forceinline__ uint2 record_word(const Prob &p, int r, int ovf, int q) {
+  if (4 * q < p.H) return reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H)[q];
+  const int q2 = q - p.H / 4;
+  if (ovf >= 0 && 4 * q2 < p.H2) return reinterpret_cast<const uint2 *>(p.hops2 + (size_t)ovf * p.H2)[q2];
+  return make_uint2(~0u, ~0u);
 }
 
 // hop count of a record (its ids; padding only at the end).  Computed from every word, so that the
@@ -347,7 +372,8 @@ __device__ __forceinline__ void gather_csr(const Prob &p, const State &s, const 
 // them, else from the CSR layout; with per-link penalties always from the CSR layout, weighted.
 template <int NP>
 __device__ __forceinline__ void gather_paths(const Prob &p, const State &s, bool per_link, const int (&r)[NP],
-                                             unsigned on, double (&sg)[NP], double (&sq)[NP], double (&Wr)[NP]) {
+                                             const int (&ovf)[NP], unsigned on, double (&sg)[NP], double (&sq)[NP],
+                                             double (&Wr)[NP]) {
   if (per_link) {
     gather_csr<NP, true>(p, s, r, on, sg, sq, Wr);
   } else if (p.H > 0) {
@@ -356,7 +382,7 @@ __device__ __forceinline__ void gather_paths(const Prob &p, const State &s, bool
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
       uint2 w[1][kMaxHopSlots / 4];
-      load_record(p, r[j], w[0]);
+      load_record(p, r[j], ovf[j], w[0]);
       double g1[1], q1[1];
       int n1[1];
       gather_records<1, 8>(s, w, (on >> j) & 1u, g1, q1, n1);
@@ -389,7 +415,7 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
   const int bl = xcd_chunk(blockIdx.x, gridDim.x);
   const int c = bl * (kThreads >> p.logG) + (t >> p.logG);
   // gathers (independent of the control record): sums of g and q along the path
-  int r0 = 0, np = 0, r = 0;
+  int r0 = 0, np = 0, r = 0, dv = -1;
   double xr = 0.0, ung = 0.0, Dc = 0.0, Wn = 1.0;
   double sg = 0.0, sq = 0.0, udc = 0.0, S0 = 0.0;
   bool on = false;
@@ -400,15 +426,16 @@ __global__ __launch_bounds__(kThreads + 64) void k_demand(Prob p, State s, const
       S0 = s.S[c];
       r0 = p.dptr[c];
       np = p.dptr[c + 1] - r0;
+      if (p.H2 > 0) dv = p.dovf[c];
     }
     on = lane < np;
     r = r0 + (on ? lane : 0);  // a lane without a path reads the demand's first (or path 0)
     const double xv = s.x[r], uv = s.uneg[r];
     xr = on ? xv : 0.0;
     ung = on ? uv : 0.0;
-    const int rr[1] = {r};
+    const int rr[1] = {r}, ro[1] = {overflow_record(dv, r, r0)};
     double g1[1], q1[1], w1[1];
-    gather_paths<1>(p, s, prm.per_link, rr, on ? 1u : 0u, g1, q1, w1);
+    gather_paths<1>(p, s, prm.per_link, rr, ro, on ? 1u : 0u, g1, q1, w1);
     sg = g1[0];
     sq = q1[0];
     Wn = on ? w1[0] : 1.0;
@@ -479,27 +506,30 @@ __global__ __launch_bounds__(kThreads) void k_demand_multi(Prob p, State s, cons
     xr[j] = ung[j] = sg[j] = sq[j] = 0.0;
     Wn[j] = 1.0;
   }
+  int dv = -1;
   if (c < p.D) {
     Dc = p.Dn[c];
     udc = s.udem[c];
     S0 = s.S[c];
     r0 = p.dptr[c];
     np = p.dptr[c + 1] - r0;
+    if (p.H2 > 0) dv = p.dovf[c];
   }
   {
-    int rr[PPL];
+    int rr[PPL], ro[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       const int idx = lane + j * Gp;
       const bool oj = idx < np;
       on |= oj ? 1u << j : 0u;
       rr[j] = r0 + (oj ? idx : 0);  // a slot without a path reads the demand's first (or path 0)
+      ro[j] = overflow_record(dv, rr[j], r0);
       const double xv = s.x[rr[j]], uv = s.uneg[rr[j]];
       xr[j] = oj ? xv : 0.0;
       ung[j] = oj ? uv : 0.0;
     }
     double W[PPL];
-    gather_paths<PPL>(p, s, prm.per_link, rr, on, sg, sq, W);
+    gather_paths<PPL>(p, s, prm.per_link, rr, ro, on, sg, sq, W);
 #pragma unroll
     for (int j = 0; j < PPL; ++j) Wn[j] = ((on >> j) & 1u) ? W[j] : 1.0;
   }
@@ -781,14 +811,14 @@ struct PathIds {
 // which the compiler waits for one at a time.  The straight-line gathers above (several loads in
 // flight) made this kernel spill: at 1,024 threads it has 128 registers a lane, and its time went up
 // (1,000-node instance, 143 -> 159 us with two paths per lane).
-__device__ __forceinline__ void gather_path_serial(const Prob &p, const State &s, int r, double &sg, double &sq, int &n) {
+__device__ __forceinline__ void gather_path_serial(const Prob &p, const State &s, int r, int ovf, double &sg,
+                                                   double &sq, int &n) {
   sg = 0.0;
   sq = 0.0;
   if (p.H > 0) {
-    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
     uint2 w[kMaxHopSlots / 4];
 #pragma unroll
-    for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) w[q] = record_word(p, r, ovf, q);
     n = 0;
 #pragma unroll
     for (int q = 0; q < kMaxHopSlots / 4; ++q) {
@@ -820,14 +850,13 @@ __device__ __forceinline__ void gather_path_serial(const Prob &p, const State &s
   }
 }
 
-__device__ __forceinline__ void gather_ids(const Prob &p, const State &s, int r, PathIds &id, double &sg,
+__device__ __forceinline__ void gather_ids(const Prob &p, const State &s, int r, int ovf, PathIds &id, double &sg,
                                            double &sq, int &n) {
   sg = 0.0;
   sq = 0.0;
   if (p.H > 0) {
-    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
 #pragma unroll
-    for (int q = 0; q < kMaxHopSlots / 4; ++q) id.w[q] = 4 * q < p.H ? rec[q] : make_uint2(~0u, ~0u);
+    for (int q = 0; q < kMaxHopSlots / 4; ++q) id.w[q] = record_word(p, r, ovf, q);
     n = 0;
 #pragma unroll
     for (int q = 0; q < kMaxHopSlots / 4; ++q) {
@@ -862,13 +891,12 @@ __device__ __forceinline__ void gather_ids(const Prob &p, const State &s, int r,
 
 // acc[e] += v for every link e of path r, its link ids read again (from the caches: the gather
 // read them in the same pass)
-__device__ __forceinline__ void scatter_path(const Prob &p, int r, double v, double *acc) {
+__device__ __forceinline__ void scatter_path(const Prob &p, int r, int ovf, double v, double *acc) {
   if (p.H > 0) {
-    const uint2 *rec = reinterpret_cast<const uint2 *>(p.hops + (size_t)r * p.H);
 #pragma unroll
     for (int q = 0; q < kMaxHopSlots / 4; ++q) {
-      if (4 * q >= p.H) break;
-      const uint2 wq = rec[q];
+      if (4 * q >= p.H + (ovf >= 0 ? p.H2 : 0)) break;
+      const uint2 wq = record_word(p, r, ovf, q);
       const unsigned e4[4] = {wq.x & 0xffffu, wq.x >> 16, wq.y & 0xffffu, wq.y >> 16};
 #pragma unroll
       for (int u = 0; u < 4; ++u)
@@ -925,12 +953,14 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
       xr[j] = ung[j] = sg[j] = sq[j] = 0.0;
       n[j] = 1;
     }
+    int dv = -1;
     if (c < p.D) {
       Dc = p.Dn[c];
       udc = s.udem[c];
       S0 = s.S[c];
       r0 = p.dptr[c];
       np = p.dptr[c + 1] - r0;
+      if (p.H2 > 0) dv = p.dovf[c];
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
         const int idx = lane + j * Gp;
@@ -940,9 +970,9 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
           xr[j] = s.x[r];
           ung[j] = s.uneg[r];
           if (KEEP)
-            gather_ids(p, s, r, ids[0], sg[j], sq[j], n[j]);
+            gather_ids(p, s, r, overflow_record(dv, r, r0), ids[0], sg[j], sq[j], n[j]);
           else
-            gather_path_serial(p, s, r, sg[j], sq[j], n[j]);
+            gather_path_serial(p, s, r, overflow_record(dv, r, r0), sg[j], sq[j], n[j]);
         }
       }
     }
@@ -985,7 +1015,7 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
         if (KEEP)
           scatter_ids(p, ids[0], xn, acc);
         else
-          scatter_path(p, r, xn, acc);
+          scatter_path(p, r, overflow_record(dv, r, r0), xn, acc);
         xsum += xn;
         ds2 += (xn - xr[j]) * (xn - xr[j]);
         dr2 += (un - L.un[j]) * (un - L.un[j]);

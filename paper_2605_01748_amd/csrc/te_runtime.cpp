@@ -91,7 +91,7 @@ hipError_t dalloc(T **p, size_t n) {
 
 struct te_ctx {
   int device = 0;
-  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0, ppl = 1, logGp = 0;
+  int32_t E = 0, P = 0, D = 0, nnz = 0, maxp = 0, G = 1, logG = 0, H = 0, H2 = 0, ppl = 1, logGp = 0;
   int32_t lsum = kLinkSumsCsc;  // link sums of the graph engine in use (Prob::lsum)
   int32_t nB_csc = 0;           // workgroups of the CSC link kernel (also the adjoint's link kernel)
   int32_t ncu = 256;            // compute units of the device
@@ -115,6 +115,8 @@ struct te_ctx {
   int32_t *d_i32 = nullptr;
   int4 *d_wtab = nullptr;
   uint16_t *d_hops = nullptr;
+  uint16_t *d_hops2 = nullptr;
+  int32_t *d_dovf = nullptr;
   double *d_Dn = nullptr;
   double *d_Cn = nullptr;
   // workgroup engine (single instance)
@@ -705,21 +707,53 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
     if (hipMemcpy(c->d_i32, pool.data(), sizeof(int32_t) * ni, hipMemcpyHostToDevice) != hipSuccess)
       return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the index pool failed"));
   }
-  // fixed-width hop records of the demand kernel (when every path fits kMaxHopSlots and every
-  // link id fits 16 bits): the row-pointer load before the link ids is then not needed
+  // fixed-width hop records of the demand kernels (when every path fits kMaxHopSlots and every
+  // link id fits 16 bits): the row-pointer load before the link ids is then not needed.  A path's
+  // first kPrimarySlots ids sit in its primary record; the paths of a demand with a longer path
+  // continue in overflow records of H2 more slots, one per path of that demand, so that paths of
+  // up to 16 hops do not pad every record to 16 slots (1,000-node instance: 5.9 hops on average,
+  // 15 at most, 15 % of the demands with a path of more than 8)
   {
     int maxh = 0;
     for (int32_t r = 0; r < c->P; ++r) maxh = std::max(maxh, c->pptr[r + 1] - c->pptr[r]);
-    c->H = (maxh + 3) & ~3;
-    if (c->H <= kMaxHopSlots && c->E < 0xffff) {
+    const int Htot = (maxh + 3) & ~3;
+    if (Htot <= kMaxHopSlots && c->E < 0xffff) {
+      c->H = std::min(Htot, kPrimarySlots);
+      c->H2 = Htot - c->H;
       std::vector<uint16_t> hops((size_t)c->P * c->H, (uint16_t)0xffff);
       for (int32_t r = 0; r < c->P; ++r)
-        for (int32_t i = c->pptr[r]; i < c->pptr[r + 1]; ++i)
+        for (int32_t i = c->pptr[r]; i < std::min(c->pptr[r + 1], c->pptr[r] + c->H); ++i)
           hops[(size_t)r * c->H + (i - c->pptr[r])] = (uint16_t)c->plinks[i];
       if (dalloc(&c->d_hops, hops.size()) != hipSuccess)
         return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
       if (hipMemcpy(c->d_hops, hops.data(), sizeof(uint16_t) * hops.size(), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the hop records failed"));
+      if (c->H2 > 0) {
+        std::vector<int32_t> dovf(c->D, -1);
+        int64_t n2 = 0;
+        for (int32_t d = 0; d < c->D; ++d) {
+          bool longp = false;
+          for (int32_t r = c->dptr[d]; r < c->dptr[d + 1]; ++r) longp = longp || c->pptr[r + 1] - c->pptr[r] > c->H;
+          if (longp) {
+            dovf[d] = (int32_t)n2;
+            n2 += c->dptr[d + 1] - c->dptr[d];
+          }
+        }
+        std::vector<uint16_t> hops2((size_t)n2 * c->H2, (uint16_t)0xffff);
+        for (int32_t d = 0; d < c->D; ++d) {
+          if (dovf[d] < 0) continue;
+          for (int32_t r = c->dptr[d]; r < c->dptr[d + 1]; ++r) {
+            const size_t rec = (size_t)(dovf[d] + (r - c->dptr[d])) * c->H2;
+            for (int32_t i = c->pptr[r] + c->H; i < c->pptr[r + 1]; ++i)
+              hops2[rec + (i - c->pptr[r] - c->H)] = (uint16_t)c->plinks[i];
+          }
+        }
+        if (dalloc(&c->d_hops2, hops2.size()) != hipSuccess || dalloc(&c->d_dovf, dovf.size()) != hipSuccess)
+          return cleanup_fail(fail(TE_ERR_OOM, "device allocation failed"));
+        if (hipMemcpy(c->d_hops2, hops2.data(), sizeof(uint16_t) * hops2.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c->d_dovf, dovf.data(), sizeof(int32_t) * dovf.size(), hipMemcpyHostToDevice) != hipSuccess)
+          return cleanup_fail(fail(TE_ERR_DEVICE, "copy of the overflow hop records failed"));
+      }
     }
   }
   te_status s = upload_values(c);
@@ -743,6 +777,9 @@ te_status te_create(int32_t n_links, const double *capacity, int32_t n_paths, co
   p.wtab = c->d_wtab;
   p.hops = c->d_hops;
   p.H = c->d_hops ? c->H : 0;
+  p.hops2 = c->d_hops2;
+  p.H2 = c->d_hops2 ? c->H2 : 0;
+  p.dovf = c->d_dovf;
   p.Dn = c->d_Dn;
   p.Cn = c->d_Cn;
   *out = c;
@@ -775,7 +812,7 @@ te_status te_info(const te_ctx *c, int64_t *sz) {
   sz[5] = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   sz[6] = c->st.nA;
   sz[7] = c->st.nB;
-  sz[8] = c->d_hops ? c->H : 0;
+  sz[8] = c->d_hops ? c->H + (c->d_hops2 ? c->H2 : 0) : 0;
   sz[9] = c->rec_K > 0 ? c->rec_gen : 0;
   sz[10] = c->lsum;
   sz[11] = c->prob.nF;
@@ -1218,7 +1255,7 @@ void te_destroy(te_ctx *c) {
   free_fwd(c->work);
   void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->d_trace, c->st.partL, c->st.w, c->st.dx2, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
-                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops};
+                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops, c->d_hops2, c->d_dovf};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_params) (void)hipHostFree(c->h_params);
