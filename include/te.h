@@ -105,15 +105,15 @@ typedef struct {
   int32_t record;      /* 1: keep the (beta, alpha) schedule and checkpoints for te_grad */
   int32_t ckpt_every;  /* te_grad checkpoint spacing in iterations; default 16 */
   int32_t block_threads; /* workgroup engine: threads per workgroup, 256, 512 or 1024; 0 (default):
-                            1024 for single solves, tuned for batches (see paths_per_lane) */
+                            tuned on the handle's first such solve (see paths_per_lane) */
   int32_t paths_per_lane; /* paths of a demand held by one lane in the demand step, 1, 2, 4 or 8 (a
                             demand with G path slots gets max(1, G / paths_per_lane) lanes); 0
                             (default): graph engine 1, or 2 for instances with at least 2^20 lane
                             slots (demands x G: there the kernel is bound by issue and bandwidth,
-                            not latency); workgroup engine 4 for single solves, and for batches
-                            the members of (block_threads, paths_per_lane) left at 0 are tuned on
-                            the batch's first such solve (every candidate timed over
-                            min(max(fixed_iters, 256), 512) iterations) and kept by the handle.
+                            not latency); workgroup engine: the members of (block_threads,
+                            paths_per_lane) left at 0 are tuned on the handle's (or batch's) first
+                            such solve (every candidate timed over min(max(fixed_iters, 256), 512)
+                            iterations; up to 12 short launches) and kept by the handle.
                             A new value for the graph engine recaptures its iteration graphs
                             (after a device-wide synchronisation). */
   int32_t warm;        /* 1: continue from the state the handle's last graph-engine solve left (rates,

@@ -134,8 +134,8 @@ class Options:
     engine: int = ENGINE_AUTO
     record: bool = False
     ckpt_every: int = 16
-    block_threads: int = 0             # workgroup engine: 256, 512, 1024; 0 = default / tuned for batches
-    paths_per_lane: int = 0            # workgroup engine: 1, 2, 4, 8; 0 = default / tuned for batches
+    block_threads: int = 0             # workgroup engine: 256, 512, 1024; 0 = tuned on the first solve
+    paths_per_lane: int = 0            # 1, 2, 4, 8; 0 = graph engine default, workgroup engine tuned
     warm: bool = False                 # continue from the handle's last graph-engine state
     trace: bool = False                # log (beta_k, alpha_k, r_k, s_k) per iteration (Problem.trace)
     link_sums: int = LINK_SUMS_AUTO    # graph engine: privatised (LDS rows) or CSC segmented link sums

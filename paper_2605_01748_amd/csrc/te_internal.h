@@ -141,12 +141,10 @@ constexpr int kMaxLinksPerBlock = 1024;
 constexpr int kThreads = 256;        // threads per workgroup of the graph-engine demand kernels
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kLinkWaves = kLinkThreads / 64;
-constexpr int kBlockThreads = 1024;  // threads of the workgroup engine for single solves
 constexpr int kScatThreads = 1024;   // threads per workgroup of the privatised-sum demand kernel
 // privatised sums: the scatter workgroup's LDS copy of the loads (8 bytes a link) and the link
 // reduction's workgroups (64 links each, at most kMaxLinkBlocks) bound the links
 constexpr int kMaxScatterLinks = 19456;
-constexpr int kBlockPathsPerLane = 4;  // paths per lane of the workgroup engine for single solves
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
 struct BatchDesc {

@@ -132,6 +132,9 @@ struct te_ctx {
   int32_t *h_flag = nullptr;  // pinned: stop flags of chunks in flight
   hipEvent_t ev0 = nullptr, ev1 = nullptr;  // timing
   hipEvent_t pe[2] = {nullptr, nullptr};    // polling of the stop flag
+  // workgroup engine: (block_threads, paths_per_lane) picked on the first solve that leaves one or
+  // both at 0, per requested pair
+  std::map<std::pair<int, int>, std::pair<int, int>> tuned;
   size_t lds_bytes = 0;
   // recorded solve for te_grad
   int32_t rec_K = 0, rec_ck = 16, rec_warm = 0;
@@ -332,6 +335,40 @@ te_status stage_params(Params **d_params, Params *h_params, hipEvent_t ev, doubl
   *h_params = p;
   HIPCHK(hipMemcpyAsync(*d_params, h_params, sizeof(Params), hipMemcpyHostToDevice, stream));
   HIPCHK(hipEventRecord(ev, stream));
+  return TE_OK;
+}
+
+// The workgroup engine's (threads, paths per lane) for a solve that left one or both at 0: every
+// candidate pair (the unspecified members vary over {1024, 512, 256} x {1, 2, 4, 8}) runs
+// launch(threads, ppl, iterations) for min(max(fixed_iters, 256), 512) iterations after a short
+// warm-up launch, timed with events on the stream; the fastest pair is returned.  The launches
+// write the caller's outputs, which the solve that follows overwrites.
+template <class Launch>
+te_status tune_block_shape(int threads, int ppl, int fixed_iters, hipStream_t stream, hipEvent_t ev0, hipEvent_t ev1,
+                           Launch &&launch, std::pair<int, int> *pick) {
+  const int K_t = std::min(std::max(fixed_iters, 256), 512);
+  const int cand_t[3] = {1024, 512, 256}, cand_p[4] = {1, 2, 4, 8};
+  float best = 0.f;
+  *pick = std::make_pair(0, 0);
+  for (int i = 0; i < 3; ++i) {
+    if (threads != 0 && cand_t[i] != threads) continue;
+    for (int k = 0; k < 4; ++k) {
+      if (ppl != 0 && cand_p[k] != ppl) continue;
+      for (int q = 0; q < 2; ++q) {  // q = 0: warm-up launch that also sets up the kernel
+        HIPCHK(hipEventRecord(ev0, stream));
+        te_status s = launch(cand_t[i], cand_p[k], q == 0 ? 8 : K_t);
+        if (s != TE_OK) return s;
+        HIPCHK(hipEventRecord(ev1, stream));
+      }
+      HIPCHK(hipEventSynchronize(ev1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+      if (pick->first == 0 || ms < best) {
+        best = ms;
+        *pick = std::make_pair(cand_t[i], cand_p[k]);
+      }
+    }
+  }
   return TE_OK;
 }
 
@@ -844,6 +881,33 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   if (engine == TE_ENGINE_AUTO) engine = c->lds_bytes <= kMaxBlockLds ? TE_ENGINE_BLOCK : TE_ENGINE_GRAPH;
   if (engine == TE_ENGINE_BLOCK && c->lds_bytes > kMaxBlockLds)
     return fail(TE_ERR_INVALID, "instance needs %zu bytes of LDS, more than one workgroup has", c->lds_bytes);
+  int bthreads = o.block_threads, bppl = o.paths_per_lane;
+  if (engine == TE_ENGINE_BLOCK && (bthreads == 0 || bppl == 0)) {
+    const std::pair<int, int> key(bthreads, bppl);
+    auto it = c->tuned.find(key);
+    if (it == c->tuned.end()) {
+      std::pair<int, int> pick;
+      Pools tp{c->d_i32, c->d_Dn, c->d_Cn, nullptr, nullptr, 0};
+      s = tune_block_shape(bthreads, bppl, o.fixed_iters, stream, c->ev0, c->ev1,
+                           [&](int th, int pl, int iters) -> te_status {
+                             te_options t;
+                             te_default_options(&t);
+                             t.fixed_iters = iters;
+                             t.project = 0;
+                             te_status st = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched,
+                                                         &c->sched_cap, &t, stream);
+                             if (st != TE_OK) return st;
+                             HIPCHK(launch_block_solve(c->d_desc, 1, tp, c->d_params, 0, x_out_dev, S_out_dev,
+                                                       c->d_bout, c->lds_bytes, th, pl, stream));
+                             return TE_OK;
+                           },
+                           &pick);
+      if (s != TE_OK) return s;
+      it = c->tuned.emplace(key, pick).first;
+    }
+    bthreads = it->second.first;
+    bppl = it->second.second;
+  }
   s = stage_params(&c->d_params, c->h_params, c->params_ev, &c->d_sched, &c->sched_cap, &o, stream);
   if (s != TE_OK) return s;
   // per-iteration trace (beta_k, alpha_k, r_k, s_k) of a solve that asks for it; a recorded solve
@@ -866,8 +930,7 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
   if (engine == TE_ENGINE_BLOCK) {
     Pools pools{c->d_i32, c->d_Dn, c->d_Cn, x0_dev, o.trace ? c->d_trace : nullptr, o.trace ? c->trace_cap : 0};
     HIPCHK(launch_block_solve(c->d_desc, 1, pools, c->d_params, o.project, x_out_dev, S_out_dev, c->d_bout,
-                              c->lds_bytes, o.block_threads ? o.block_threads : kBlockThreads,
-                              o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane, stream));
+                              c->lds_bytes, bthreads, bppl, stream));
   } else {
     s = select_graph_shape(c, o);
     if (s != TE_OK) return s;
@@ -1001,8 +1064,8 @@ te_status te_solve(te_ctx *c, const te_options *opt, void *hip_stream, const flo
     }
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    fill_stats(stats, fin, engine, ms, o.block_threads ? o.block_threads : kBlockThreads,
-               engine == TE_ENGINE_BLOCK ? (o.paths_per_lane ? o.paths_per_lane : kBlockPathsPerLane) : c->ppl);
+    fill_stats(stats, fin, engine, ms, engine == TE_ENGINE_BLOCK ? bthreads : 0,
+               engine == TE_ENGINE_BLOCK ? bppl : c->ppl);
     if (!std::isfinite(fin.r) || !std::isfinite(fin.s))
       return fail(TE_ERR_NUMERIC, "non-finite residuals (r=%g, s=%g)", fin.r, fin.s);
   }
@@ -1416,39 +1479,22 @@ te_status te_solve_batch(te_batch *b, const te_options *opt, void *hip_stream, f
     const std::pair<int, int> key(threads, ppl);
     auto it = b->tuned.find(key);
     if (it == b->tuned.end()) {
-      // tuning on the first such solve: each candidate pair (the unspecified members vary) runs the
-      // batch for min(max(fixed_iters, 256), 512) iterations after a short warm-up launch, timed
-      // with events; the fastest is kept by the handle for later solves too (the outputs are
-      // overwritten by the solve below)
-      const int K_t = std::min(std::max(o.fixed_iters, 256), 512);
-      const int cand_t[3] = {1024, 512, 256}, cand_p[4] = {1, 2, 4, 8};
-      float best = 0.f;
-      std::pair<int, int> pick(0, 0);
-      for (int i = 0; i < 3; ++i) {
-        if (threads != 0 && cand_t[i] != threads) continue;
-        for (int k = 0; k < 4; ++k) {
-          if (ppl != 0 && cand_p[k] != ppl) continue;
-          for (int q = 0; q < 2; ++q) {  // q = 0: warm-up launch that also sets up the kernel
-            te_options t;
-            te_default_options(&t);
-            t.fixed_iters = q == 0 ? 8 : K_t;
-            t.project = 0;
-            s = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched, &b->sched_cap, &t, stream);
-            if (s != TE_OK) return s;
-            HIPCHK(hipEventRecord(b->ev0, stream));
-            HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev, b->d_out,
-                                      b->lds_bytes, cand_t[i], cand_p[k], stream));
-            HIPCHK(hipEventRecord(b->ev1, stream));
-          }
-          HIPCHK(hipEventSynchronize(b->ev1));
-          float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-          if (pick.first == 0 || ms < best) {
-            best = ms;
-            pick = std::make_pair(cand_t[i], cand_p[k]);
-          }
-        }
-      }
+      std::pair<int, int> pick;
+      s = tune_block_shape(threads, ppl, o.fixed_iters, stream, b->ev0, b->ev1,
+                           [&](int th, int pl, int iters) -> te_status {
+                             te_options t;
+                             te_default_options(&t);
+                             t.fixed_iters = iters;
+                             t.project = 0;
+                             te_status st = stage_params(&b->d_params, b->h_params, b->params_ev, &b->d_sched,
+                                                         &b->sched_cap, &t, stream);
+                             if (st != TE_OK) return st;
+                             HIPCHK(launch_block_solve(b->d_desc, b->n, pools, b->d_params, 0, x_out_dev, S_out_dev,
+                                                       b->d_out, b->lds_bytes, th, pl, stream));
+                             return TE_OK;
+                           },
+                           &pick);
+      if (s != TE_OK) return s;
       it = b->tuned.emplace(key, pick).first;
     }
     threads = it->second.first;

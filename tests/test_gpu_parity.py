@@ -308,6 +308,24 @@ def test_batch_tuned_workgroup_size(te):
     print(f"tuned for 64 scenarios: {t} threads, {q} paths per lane")
 
 
+def test_single_solve_tuned_workgroup_size(te, c1):
+    """A single workgroup-engine solve with block_threads = paths_per_lane = 0 tunes the pair on the
+    handle's first such solve, keeps it, and equals the forced solve with that pair."""
+    prob = te.Problem(c1)
+    o = te.Options(fixed_iters=64, engine=te.ENGINE_BLOCK)
+    x1, _, st1 = prob.solve(o)
+    t, q = st1["block_threads"], st1["paths_per_lane"]
+    assert t in (256, 512, 1024) and q in (1, 2, 4, 8) and st1["engine"] == te.ENGINE_BLOCK
+    x2, _, st2 = prob.solve(o)
+    assert (st2["block_threads"], st2["paths_per_lane"]) == (t, q)
+    np.testing.assert_array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    x3, _, _ = prob.solve(te.Options(fixed_iters=64, engine=te.ENGINE_BLOCK, block_threads=t, paths_per_lane=q))
+    np.testing.assert_array_equal(x1.cpu().numpy(), x3.cpu().numpy())
+    _, _, st4 = prob.solve(te.Options(fixed_iters=64, engine=te.ENGINE_BLOCK, block_threads=256))
+    assert st4["block_threads"] == 256 and st4["paths_per_lane"] in (1, 2, 4, 8)
+    print(f"tuned for the 20-node instance: {t} threads, {q} paths per lane")
+
+
 @pytest.mark.parametrize("ppl", [2, 4, 8])
 @pytest.mark.parametrize("name", ["waxman20", "ragged0"])
 def test_parity_block_paths_per_lane(te, c1, ppl, name):
