@@ -226,6 +226,36 @@ __device__ __forceinline__ void F_eval(double S, const LaneN<PPL> &L, const Dem 
 // the correction or the bracket falls below 1e-13 max(1, |S|) (normalised units, where F's
 // rounding noise is ~1e-16 of its O(1) terms).  The root is the same as the oracle's to that
 // tolerance; only the path to it is shorter.
+// alpha = 0: F is piecewise linear, with kinks where the demand hinge t = S - D + u_dem or a
+// path's branch b_r = a_r - h(S) >= n_r u_neg_r changes (the same expressions as F_eval's).  True
+// when one of them changes between S and Sn for this lane.
+__device__ __forceinline__ bool kink_between(double S, double Sn, const Lane &L, const Dem &c) {
+  const double t0 = S - c.D + c.u, t1 = Sn - c.D + c.u;
+  if ((t0 > 0.0) != (t1 > 0.0)) return true;
+  if (!L.on) return false;
+  const double h0 = fmax(t0, 0.0) - c.binv, h1 = fmax(t1, 0.0) - c.binv;
+  const double th = L.n * L.un;
+  return (L.a - h0 >= th) != (L.a - h1 >= th);
+}
+
+template <int PPL>
+__device__ __forceinline__ bool kink_between(double S, double Sn, const LaneN<PPL> &L, const Dem &c) {
+  const double t0 = S - c.D + c.u, t1 = Sn - c.D + c.u;
+  if ((t0 > 0.0) != (t1 > 0.0)) return true;
+  const double h0 = fmax(t0, 0.0) - c.binv, h1 = fmax(t1, 0.0) - c.binv;
+  bool k = false;
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const double th = L.n[j] * L.un[j];
+    k = k || (((L.on >> j) & 1u) && ((L.a[j] - h0 >= th) != (L.a[j] - h1 >= th)));
+  }
+  return k;
+}
+
+// true on every lane of a group of G lanes (aligned, a power of two) when it is true on one of them
+// (the group sum of the F evaluation, applied to a flag)
+__device__ __forceinline__ bool group_any(bool pred, int G) { return group_sum_d(pred ? 1.0 : 0.0, G) > 0.0; }
+
 template <class LaneT>
 __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *evals) {
   const double tol = 1e-13;
@@ -252,6 +282,10 @@ __device__ double sum_root(double S, const LaneT &L, const Dem &c, int G, int *e
       if (fabs(step) <= tol * scale) return S - step;  // correction below tolerance
       Sn = S - step;
       ok = Sn > lo && Sn < hi && !(c.alpha > 0.0 && !(Sn > 0.0));
+      // alpha = 0: on a linear piece of F the Newton point is its root; when no kink lies between
+      // S and Sn it is returned without the evaluation that would only confirm it (F(Sn) is zero
+      // to rounding there)
+      if (ok && c.alpha == 0.0 && !group_any(kink_between(S, Sn, L, c), G)) return Sn;
     }
     if (!ok) {
       if (lo > -INFINITY && hi < INFINITY) {

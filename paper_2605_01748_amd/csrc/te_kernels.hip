@@ -42,24 +42,26 @@ __device__ __forceinline__ void prefetch_ctrl(const State &s, int par, CtrlPrefe
   cp.v[1] = 0.0;
   cp.v[2] = -INFINITY;
   cp.v[3] = -INFINITY;
-  // all rows' loads are issued before the first add (nB <= 8 * 64), so they take one round trip
+  // all rows' loads are issued before the first add (nB <= 8 * 64), so they take one round trip:
+  // they are unconditional (a slot past the rows reads the last row again: harmless for the maxima,
+  // and masked out of the sums by a product -- a select, or a load inside a branch, would be waited
+  // for before the next load is issued)
   const double2 *pb = reinterpret_cast<const double2 *>(s.partB + (size_t)(par ^ 1) * s.nB * 4);
   constexpr int R = kMaxLinkBlocks / 64;
   double2 lo[R], hi[R];
+  double m[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     const int i = (threadIdx.x & 63) + 64 * u;
-    lo[u] = make_double2(0.0, 0.0);
-    hi[u] = make_double2(-INFINITY, -INFINITY);
-    if (i < s.nB) {
-      lo[u] = pb[2 * i];
-      hi[u] = pb[2 * i + 1];
-    }
+    const int ic = i < s.nB ? i : s.nB - 1;
+    m[u] = i < s.nB ? 1.0 : 0.0;
+    lo[u] = pb[2 * ic];
+    hi[u] = pb[2 * ic + 1];
   }
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    cp.v[0] += lo[u].x;
-    cp.v[1] += lo[u].y;
+    cp.v[0] = fma(lo[u].x, m[u], cp.v[0]);
+    cp.v[1] = fma(lo[u].y, m[u], cp.v[1]);
     cp.v[2] = fmax(cp.v[2], hi[u].x);
     cp.v[3] = fmax(cp.v[3], hi[u].y);
   }
