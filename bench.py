@@ -635,7 +635,9 @@ def main():
         w_small = min(optimality(Sm[offs[i]:offs[i + 1]], gold4[f"S{i}"], THETA * 100.0) for i in range(63))
         o_big = optimality(Sm[offs[63]:offs[63] + inst.n_demands], opt_S, THETA * scale)
         t_mixed = time_solves(torch, bm, om, 3, 1)
-        t_small = sum(time_solves(torch, p, te.Options(fixed_iters=K_star), 1, 0) for p in probs[:63])
+        o_small = te.Options(fixed_iters=K_star, block_threads=st_p["block_threads"],
+                             paths_per_lane=st_p["paths_per_lane"])  # the pair tuned for the plain solves
+        t_small = sum(time_solves(torch, p, o_small, 1, 0) for p in probs[:63])
         t_big = time_solves(torch, prob, te.Options(fixed_iters=K_star, **gopt), 3, 1)
         mixed = {"workload": "63 20-node failure scenarios + the 150-node instance, one union solve on the graph engine",
                  "K": K_star, "engine": "graph" if stm[0]["engine"] == 1 else "block",
