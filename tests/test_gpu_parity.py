@@ -757,12 +757,14 @@ _LSUM_CASES = {
 }
 
 
+@pytest.mark.parametrize("ppl", [0, 2])
 @pytest.mark.parametrize("lsum", ["private", "csc"])
 @pytest.mark.parametrize("name", sorted(_LSUM_CASES))
-def test_parity_link_sum_variants(te, name, lsum):
+def test_parity_link_sum_variants(te, name, lsum, ppl):
     """Both ways of forming the link loads (privatised LDS rows reduced per link, or segmented sums
     over the link -> path list) against the oracle, schedule replayed, on instances with 1 to 64 paths
-    per demand and hop-record or CSR path layouts; the handle switches between them."""
+    per demand and hop-record or CSR path layouts; the handle switches between them; one and two
+    paths per lane."""
     inst = _LSUM_CASES[name]()
     K = 64
     r, sb, sa = _oracle_run(inst, K)
@@ -771,7 +773,7 @@ def test_parity_link_sum_variants(te, name, lsum):
     other = te.LINK_SUMS_CSC if lsum == "private" else te.LINK_SUMS_PRIVATE
     for ls in (want, other, want):
         x, S, st = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, link_sums=ls,
-                                         sched_beta=sb, sched_alpha=sa))
+                                         paths_per_lane=ppl, sched_beta=sb, sched_alpha=sa))
         info = prob.info()
         assert info["link_sums"] == ls
         assert (info["hop_slots"] == 0) == (name == "ragged_long")
