@@ -377,12 +377,17 @@ def main():
     info = prob.info()
     info_ppl = run(1, project=False)[2]["paths_per_lane"]
     names, kr, it = roofline_of(inst, info, ms_dem, ms_link)
-    dom = names[0] if ms_dem >= ms_link else names[1]
+    # the kernel carrying the demand step: it holds all of B_iter but the link step's 40 E (the two
+    # kernels' launch durations are within a few percent of each other on this instance, so which is
+    # longer changes from box to box; both are reported under "kernels")
+    dom = names[0]
     roofline = {"bound": "hbm", "achieved": kr[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kr[dom]["frac"], "traffic": measured_traffic(profiled_name(dom, info_ppl)), "kernel": dom,
                 "bytes_per_launch": kr[dom]["algorithmic_bytes"], "avg_launch_us": kr[dom]["avg_launch_us"],
                 "bytes_basis": "algorithmic bytes of the kernel's steps: demand step 4 nnz + 4 (P+1) + 16 P + 16 D, "
                                "link step 40 E (int32 indices, FP32 state, FP64 loads)",
+                "kernel_choice": "the kernel carrying the demand step (the larger share of B_iter by far; the two "
+                                 "per-iteration kernels take about the same time)",
                 "per_iteration": it, "kernels": kr,
                 "link_sums": "private" if info["link_sums"] == 1 else "csc",
                 "scatter_workgroups": info["scatter_workgroups"]}
