@@ -97,11 +97,14 @@ def measured_traffic(kernel, path=None):
     return None if k is None else int(k["traffic_bytes"])
 
 
-def profiled_name(kernel, ppl):
+LINK_SUMS_NAME = {1: "private", 2: "csc", 3: "private-atomic"}
+
+
+def profiled_name(kernel, ppl, lists=False):
     """The name a profile gives a per-iteration kernel: the demand kernels carry their paths per lane
-    as a template argument."""
+    (and the scatter kernel whether it sums by link lists) as template arguments."""
     if kernel == "k_demand_scatter":
-        return f"k_demand_scatter<{ppl}>"
+        return f"k_demand_scatter<{ppl}, {'true' if lists else 'false'}>"
     if kernel == "k_demand" and ppl > 1:
         return f"k_demand_multi<{ppl}>"
     return kernel
@@ -124,15 +127,16 @@ def layout_bytes(inst, info):
       demand kernel: link ids (16-bit hop records 2 nnz, or row pointers 4 (P + 1) + int32 ids 4 nnz),
                      x and u_neg read+write 32 P, (g, q) pairs 16 E, per demand pointer 4 + D 8 +
                      u_dem and S read+write 32 -> 44 D; with privatised link sums also the rows of
-                     partial loads written, 8 E per scatter workgroup;
+                     partial loads written, 8 E per scatter workgroup, and the link lists read, 2 bytes
+                     an entry (headers and padding included);
       link kernel:   privatised: those rows read, 8 E per row, (g, q) read+write 32 E, C 8 E, CSC
                      pointers 8 E; CSC: path ids 4 nnz, rates 8 P (FP64), (g, q) read+write 32 E,
                      C 8 E, non-empty-link tables 8 E."""
     P, D, E, nnz = inst.n_paths, inst.n_demands, inst.n_links, inst.nnz
     ids = 2 * nnz if info["hop_slots"] > 0 else 4 * (P + 1) + 4 * nnz
-    if info["link_sums"] == 1:
+    if info["link_sums"] in (1, 3):
         rows = 8 * E * info["scatter_workgroups"]
-        return ids + 32 * P + 16 * E + 44 * D + rows, rows + 48 * E
+        return ids + 32 * P + 16 * E + 44 * D + rows + 2 * info.get("list_entries", 0), rows + 48 * E
     return ids + 32 * P + 16 * E + 44 * D, 4 * nnz + 8 * P + 48 * E
 
 
@@ -140,7 +144,7 @@ def roofline_of(inst, info, ms_dem, ms_link):
     """Roofline figures of the two per-iteration kernels (mean launch durations ms_dem, ms_link)."""
     a_dem, a_link = b_iter_shares(inst)
     l_dem, l_link = layout_bytes(inst, info)
-    names = ("k_demand_scatter", "k_link_reduce") if info["link_sums"] == 1 else ("k_demand", "k_link")
+    names = ("k_demand_scatter", "k_link_reduce") if info["link_sums"] in (1, 3) else ("k_demand", "k_link")
     t_it = (ms_dem + ms_link) * 1e-3
     out = {}
     for name, ms, a, l in ((names[0], ms_dem, a_dem, l_dem), (names[1], ms_link, a_link, l_link)):
@@ -226,7 +230,8 @@ def large_run(args, torch, te, W, dev, with_oracle=True):
     torch.cuda.synchronize()
     ms_iter = (time.perf_counter() - t1) * 1e3 / 64
     for nm in names:  # counters of the same kernels (summary committed under profiles/), if current
-        kr[nm]["traffic"] = measured_traffic(profiled_name(nm, st64["paths_per_lane"]), TRAFFIC_FILE_LARGE)
+        kr[nm]["traffic"] = measured_traffic(profiled_name(nm, st64["paths_per_lane"], info["list_passes"] > 0),
+                                             TRAFFIC_FILE_LARGE)
     err = None
     if with_oracle:
         import oracle as O
@@ -241,7 +246,7 @@ def large_run(args, torch, te, W, dev, with_oracle=True):
                        "all ordered pairs, 1+Pareto(1.2) gravity weights, k=4 latency-shortest paths",
            "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
            "ms_per_iteration": round(ms_iter, 4), "demand_paths_per_lane": st64["paths_per_lane"],
-           "link_sums": "private" if info["link_sums"] == 1 else "csc",
+           "link_sums": LINK_SUMS_NAME[info["link_sums"]], "list_passes": info["list_passes"],
            "scatter_workgroups": info["scatter_workgroups"], "hop_slots": info["hop_slots"],
            "per_iteration": it, "kernels": kr, "error_vs_fp64_oracle": err}
     del prob
@@ -299,7 +304,7 @@ def main():
     ap.add_argument("--paths-per-lane", type=int, default=0)
     ap.add_argument("--large", action="store_true")
     ap.add_argument("--cache-dir", default=None)
-    ap.add_argument("--link-sums", type=int, default=0, help="graph engine link sums: 0 auto, 1 private, 2 csc")
+    ap.add_argument("--link-sums", type=int, default=0, help="graph engine link sums: 0 auto, 1 private (link lists), 2 csc, 3 private with atomic adds")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU (got --gpus {args.gpus}); sharding across GPUs is "
@@ -382,14 +387,15 @@ def main():
     # longer changes from box to box; both are reported under "kernels")
     dom = names[0]
     roofline = {"bound": "hbm", "achieved": kr[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kr[dom]["frac"], "traffic": measured_traffic(profiled_name(dom, info_ppl)), "kernel": dom,
+                "frac": kr[dom]["frac"], "traffic": measured_traffic(profiled_name(dom, info_ppl, info["list_passes"] > 0)),
+                "kernel": dom,
                 "bytes_per_launch": kr[dom]["algorithmic_bytes"], "avg_launch_us": kr[dom]["avg_launch_us"],
                 "bytes_basis": "algorithmic bytes of the kernel's steps: demand step 4 nnz + 4 (P+1) + 16 P + 16 D, "
                                "link step 40 E (int32 indices, FP32 state, FP64 loads)",
                 "kernel_choice": "the kernel carrying the demand step (the larger share of B_iter by far; the two "
                                  "per-iteration kernels take about the same time)",
                 "per_iteration": it, "kernels": kr,
-                "link_sums": "private" if info["link_sums"] == 1 else "csc",
+                "link_sums": LINK_SUMS_NAME[info["link_sums"]],
                 "scatter_workgroups": info["scatter_workgroups"]}
     log(f"kernels: {kr}; iteration {it}")
 

@@ -81,8 +81,14 @@ enum {
 enum {
   TE_LINK_SUMS_AUTO = 0,
   TE_LINK_SUMS_PRIVATE = 1, /* every demand workgroup adds its paths' rates into its own copy of the link
-                               loads (LDS), rows reduced per link in a second kernel */
-  TE_LINK_SUMS_CSC = 2      /* segmented sums over the link -> path incidence list */
+                               loads (LDS), rows reduced per link in a second kernel; the workgroup
+                               keeps a chunk of its paths' new rates in LDS and adds them by
+                               segmented sums over the chunk's own link -> path list (built at
+                               te_create or on the switch), or, where one pass of rates does not
+                               fit beside the loads, as TE_LINK_SUMS_PRIVATE_ATOMIC */
+  TE_LINK_SUMS_CSC = 2,     /* segmented sums over the link -> path incidence list */
+  TE_LINK_SUMS_PRIVATE_ATOMIC = 3 /* privatised as TE_LINK_SUMS_PRIVATE, one LDS atomic addition per
+                                     path-link incidence */
 };
 
 typedef struct {
@@ -131,8 +137,8 @@ typedef struct {
                           r_k, s_k (section 3.4), read back with te_trace (a recorded solve logs them
                           anyway); te_solve only, either engine */
   int32_t link_sums;   /* graph engine, how the link loads sum_{r on e} x_r are formed: TE_LINK_SUMS_*;
-                          0 (default): privatised for instances with at least 2^20 lane slots (demands x
-                          G) and at most 19,456 links, else CSC.
+                          0 (default): privatised (TE_LINK_SUMS_PRIVATE) for instances with at least 2^20
+                          lane slots (demands x G) and at most 19,456 links, else CSC.
                           A change recaptures the iteration graphs (after a device-wide synchronisation). */
   int32_t per_link;    /* 1: per-link penalties (the conclusion's learning rates adaptive across parts of
                           the topology, read as: link e's consensus and capacity constraints carry the
@@ -302,9 +308,10 @@ void te_destroy_batch(te_batch *batch);
  * path of the demand kernel's hop records (0: it reads the CSR path layout instead), the
  * generation of the recording te_grad would use (0: none; every recorded solve and every
  * te_update changes it, and te_update discards the recording), the graph engine's link sums in use
- * (TE_LINK_SUMS_PRIVATE or TE_LINK_SUMS_CSC) and its privatised-sum workgroups (0 with CSC sums).
- * The demand and link workgroups are those of the link sums in use. */
-te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [12] */);
+ * (TE_LINK_SUMS_*) and its privatised-sum workgroups (0 with CSC sums), and with TE_LINK_SUMS_PRIVATE
+ * the passes per chunk of its link lists and their 16-bit entries (both 0 where the privatised sums
+ * add one incidence at a time). The demand and link workgroups are those of the link sums in use. */
+te_status te_info(const te_ctx *ctx, int64_t *sizes_out /* [14] */);
 
 /*
  * Per-iteration trace of the handle's last te_solve, when it ran with opt->trace = 1 or

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libte_gate.so")
 TE_OK, TE_ERR_INVALID, TE_ERR_OOM, TE_ERR_DEVICE, TE_ERR_NUMERIC, TE_ERR_STATE = range(6)
 TE_CONVERGED, TE_HIT_MAX_ITERS, TE_HIT_ALPHA_MAX, TE_HIT_BETA_BOUND = 1, 2, 4, 8
 ENGINE_AUTO, ENGINE_GRAPH, ENGINE_BLOCK = 0, 1, 2
-LINK_SUMS_AUTO, LINK_SUMS_PRIVATE, LINK_SUMS_CSC = 0, 1, 2
+LINK_SUMS_AUTO, LINK_SUMS_PRIVATE, LINK_SUMS_CSC, LINK_SUMS_PRIVATE_ATOMIC = 0, 1, 2, 3
 
 API = ["te_default_options", "te_validate", "te_create", "te_update", "te_solve", "te_grad", "te_create_batch",
        "te_solve_batch", "te_kernel_times", "te_project", "te_project_rates", "te_project_rates_static", "te_get_state", "te_trace", "te_destroy", "te_destroy_batch",
@@ -219,12 +219,13 @@ class Problem:
         self.n_links, self.n_paths, self.n_demands = cap.shape[0], pptr.shape[0] - 1, dem.shape[0]
 
     def info(self):
-        sz = np.zeros(12, np.int64)
+        sz = np.zeros(14, np.int64)
         _check(library().te_info(self._h, sz.ctypes.data))
         return dict(n_links=int(sz[0]), n_paths=int(sz[1]), n_demands=int(sz[2]), nnz=int(sz[3]),
                     max_paths=int(sz[4]), auto_engine=int(sz[5]), demand_workgroups=int(sz[6]),
                     link_workgroups=int(sz[7]), hop_slots=int(sz[8]), record_gen=int(sz[9]),
-                    link_sums=int(sz[10]), scatter_workgroups=int(sz[11]))
+                    link_sums=int(sz[10]), scatter_workgroups=int(sz[11]), list_passes=int(sz[12]),
+                    list_entries=int(sz[13]))
 
     def update(self, capacity=None, demand=None):
         c = None if capacity is None else np.ascontiguousarray(capacity, np.float64)

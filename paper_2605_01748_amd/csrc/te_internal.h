@@ -83,12 +83,25 @@ struct Prob {
   // privatised sums: passes of kScatThreads / 2^logGp demands, spw consecutive passes per scatter
   // workgroup, nF workgroups (rows of partial loads)
   int32_t npass, spw, nF;
+  // privatised sums by link lists (cpp > 0): a scatter workgroup takes its passes in chunks of cpp
+  // (cpw chunks); a chunk's new rates stay in LDS (path r at r minus the chunk's first path, slot
+  // zslot holding 0) and are summed per link over the chunk's list.  The list holds the rate slots of
+  // each link's paths in pieces of at most kPieceLen, 64 pieces to a group; group g is lgrp[g] =
+  // {offset into lent (a multiple of 8), blocks}: 64 header entries (the piece's link, bit 15 when
+  // the link has other pieces, 0xffff for no piece), then blocks of 512 entries, block b holding
+  // slots 8 b .. 8 b + 7 of piece i at 8 i .. 8 i + 7 (zslot past a piece's end).
+  // lchk[b * cpw + k] = {first group, end, first path, 0} of chunk k of workgroup b.  cpp = 0: one
+  // LDS atomic addition per incidence instead.
+  int32_t cpp, cpw, zslot;
+  const uint16_t *lent;
+  const int2 *lgrp;
+  const int4 *lchk;
   // nullable [D]: per-demand unit scale of the outputs (a batch solved as the union of its
   // instances, each in its own units), in place of the handle's one scale
   const double *dscale;
 };
 
-enum { kLinkSumsPrivate = 1, kLinkSumsCsc = 2 };
+enum { kLinkSumsPrivate = 1, kLinkSumsCsc = 2, kLinkSumsPrivateAtomic = 3 };
 
 constexpr int kMaxHopSlots = 16;
 constexpr int kPrimarySlots = 8;  // slots of a path's primary hop record
@@ -142,9 +155,12 @@ constexpr int kThreads = 256;        // threads per workgroup of the graph-engin
 constexpr int kLinkThreads = 1024;   // threads per workgroup of the link kernels (16 wavefronts)
 constexpr int kLinkWaves = kLinkThreads / 64;
 constexpr int kScatThreads = 1024;   // threads per workgroup of the privatised-sum demand kernel
+constexpr int kScatWaves = kScatThreads / 64;
+constexpr int kPieceLen = 32;  // link-list entries of a piece, at most (four blocks of 8)
 // privatised sums: the scatter workgroup's LDS copy of the loads (8 bytes a link) and the link
 // reduction's workgroups (64 links each, at most kMaxLinkBlocks) bound the links
 constexpr int kMaxScatterLinks = 19456;
+constexpr int kScatLds = 8 * kMaxScatterLinks;  // dynamic LDS of a scatter workgroup, at most (bytes)
 
 // Workgroup-engine instance descriptor: offsets into concatenated arrays.
 struct BatchDesc {

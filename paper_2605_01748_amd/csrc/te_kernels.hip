@@ -659,6 +659,52 @@ __device__ __forceinline__ void seg_rows_sum(const I *lpf, const T *vals, int k0
   }
 }
 
+// rates of eight slots (one 16-byte block row of a link-list piece) into two partial sums
+__device__ __forceinline__ void add_slots(const double *xs, uint4 q, double &v0, double &v1) {
+  v0 += xs[q.x & 0xffffu];
+  v1 += xs[q.x >> 16];
+  v0 += xs[q.y & 0xffffu];
+  v1 += xs[q.y >> 16];
+  v0 += xs[q.z & 0xffffu];
+  v1 += xs[q.z >> 16];
+  v0 += xs[q.w & 0xffffu];
+  v1 += xs[q.w >> 16];
+}
+
+// the sum v of lane's piece of a group goes to acc at the piece's link: an atomic addition where the
+// link has other pieces, else a plain one (no other lane of the workgroup adds to it in the chunk)
+__device__ __forceinline__ void add_piece(unsigned lk, double v, double *acc) {
+  if (lk == 0xffffu) return;
+  const int e = (int)(lk & 0x7fffu);
+  if (lk & 0x8000u)
+    atomicAdd(&acc[e], v);
+  else
+    acc[e] += v;
+}
+
+// A chunk's link-list sums (Prob::lent): wavefront w of the scatter workgroup takes groups g0 + w,
+// g0 + w + 16, ... of the chunk's groups [g0, g1), every block load of a group issued before the
+// first is used; lane i sums the rates of piece i of a group.  (Two groups in flight at a time
+// spilled registers in the two-paths-per-lane kernel and ran slower.)
+__device__ __forceinline__ void list_sums(const Prob &p, int g0, int g1, const double *xs, double *acc) {
+  constexpr int NB = kPieceLen / 8;
+  const int lane = threadIdx.x & 63;
+  for (int g = g0 + (threadIdx.x >> 6); g < g1; g += kScatWaves) {  // uniform in the wavefront
+    const int2 gd = p.lgrp[g];
+    const uint16_t *gh = p.lent + gd.x;
+    const unsigned lk = gh[lane];
+    const uint4 *gb = reinterpret_cast<const uint4 *>(gh + 64) + lane;
+    uint4 q[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) q[b] = gb[64 * (b < gd.y ? b : 0)];
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      if (b < gd.y) add_slots(xs, q[b], v0, v1);
+    add_piece(lk, v0 + v1, acc);
+  }
+}
+
 // ------------------------------------------------------------------------------------------
 // Step a3 + a4: link loads by segmented FP64 sums over the CSC lists, capacity/consensus duals.
 // Workgroup b owns a contiguous range of non-empty links holding ~nnz/nB CSC entries; each
@@ -924,18 +970,25 @@ __device__ __forceinline__ void scatter_ids(const Prob &p, const PathIds &id, do
   }
 }
 
-// KEEP: the gather's link ids stay in registers for the scatter (one path per lane), or are read
-// again (several paths per lane, where keeping them would spill)
-template <int PPL>
+// With link lists (p.cpp > 0) the new rates of a chunk of passes go to LDS, and after the chunk the
+// workgroup sums them per link over the chunk's list (one LDS addition per piece of a link's run,
+// not one per incidence).  Without,
+// every incidence is an LDS atomic addition; KEEP: the gather's link ids stay in registers for it
+// (one path per lane), or are read again (several paths per lane, where keeping them would spill).
+template <int PPL, bool LISTS>
 __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s, const Params *prmp, int par) {
-  constexpr bool KEEP = PPL == 1;
+  constexpr bool KEEP = PPL == 1 && !LISTS;
   const Params &prm = *prmp;
-  extern __shared__ double acc[];  // [E]: this workgroup's share of every link load
+  // [E]: this workgroup's share of every link load; with link lists then [zslot + 1]: the new rates
+  // of the current chunk's paths
+  extern __shared__ double acc[];
+  double *xs = acc + p.E;
   __shared__ Ctrl cs;
   CtrlPrefetch cp;
   const int t = threadIdx.x;
   if (t < 64) prefetch_ctrl(s, par, cp);
   for (int e = t; e < p.E; e += kScatThreads) acc[e] = 0.0;
+  if (LISTS && t == 0) xs[p.zslot] = 0.0;
   const int logGp = p.logGp, Gp = 1 << logGp;
   const int lane = t & (Gp - 1);
   const int per = kScatThreads >> logGp;
@@ -944,6 +997,8 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
   double ds2 = 0.0, dr2 = 0.0, dem_v = -INFINITY;
   for (int ps = ps0; ps < ps1; ++ps) {  // bounds uniform in the workgroup
     const int c = ps * per + (t >> logGp);
+    const int kc = LISTS ? (ps - ps0) / p.cpp : 0;                // the pass's chunk
+    const int rlo = LISTS ? p.lchk[(size_t)bl * p.cpw + kc].z : 0;  // its first path
     int r0 = 0, np = 0;
     double Dc = 0.0, udc = 0.0, S0 = 0.0;
     double xr[PPL], ung[PPL], sg[PPL], sq[PPL];
@@ -1014,7 +1069,9 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
         const double un = fmax(L.un[j] - xn, 0.0);
         s.xo[r] = xn;
         s.unego[r] = un;
-        if (KEEP)
+        if (LISTS)
+          xs[r - rlo] = xn;
+        else if (KEEP)
           scatter_ids(p, ids[0], xn, acc);
         else
           scatter_path(p, r, overflow_record(dv, r, r0), xn, acc);
@@ -1030,6 +1087,12 @@ __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s
         dr2 += (ud - dm.u) * (ud - dm.u);
         dem_v = fmax(dem_v, (Ssum - dm.D) / dm.D);
       }
+    }
+    if (LISTS && ((ps - ps0) % p.cpp == p.cpp - 1 || ps == ps1 - 1)) {  // the chunk's last pass
+      __syncthreads();  // the chunk's rates are in LDS
+      const int4 ch = p.lchk[(size_t)bl * p.cpw + kc];
+      list_sums(p, ch.x, ch.y, xs, acc);
+      __syncthreads();  // and read, before the next chunk's overwrite them
     }
   }
   wave_partials(ds2, dr2, dem_v, s.partA + ((size_t)par * s.nA + bl) * (kScatThreads / 64) * 4);
@@ -1948,7 +2011,7 @@ static void launch_demand_k(K kern, int threads, const Prob &p, const State &s, 
 template <class K>
 static void launch_scatter_k(K kern, const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
                              hipEvent_t ev0, hipEvent_t ev1) {
-  const size_t lds = sizeof(double) * (size_t)p.E;
+  const size_t lds = sizeof(double) * ((size_t)p.E + (p.cpp > 0 ? (size_t)p.zslot + 1 : 0));
   if (ev0)
     hipExtLaunchKernelGGL(kern, dim3(p.nF), dim3(kScatThreads), lds, st, ev0, ev1, 0, p, s, prm, par);
   else
@@ -1958,11 +2021,20 @@ static void launch_scatter_k(K kern, const Prob &p, const State &s, const Params
 static void launch_demand_kernel(const Prob &p, const State &s, const Params *prm, int par, hipStream_t st,
                                  hipEvent_t ev0, hipEvent_t ev1) {
   if (p.lsum == kLinkSumsPrivate) {
-    switch (p.ppl) {
-      case 2: launch_scatter_k(k_demand_scatter<2>, p, s, prm, par, st, ev0, ev1); break;
-      case 4: launch_scatter_k(k_demand_scatter<4>, p, s, prm, par, st, ev0, ev1); break;
-      case 8: launch_scatter_k(k_demand_scatter<8>, p, s, prm, par, st, ev0, ev1); break;
-      default: launch_scatter_k(k_demand_scatter<1>, p, s, prm, par, st, ev0, ev1);
+    if (p.cpp > 0) {
+      switch (p.ppl) {
+        case 2: launch_scatter_k(k_demand_scatter<2, true>, p, s, prm, par, st, ev0, ev1); break;
+        case 4: launch_scatter_k(k_demand_scatter<4, true>, p, s, prm, par, st, ev0, ev1); break;
+        case 8: launch_scatter_k(k_demand_scatter<8, true>, p, s, prm, par, st, ev0, ev1); break;
+        default: launch_scatter_k(k_demand_scatter<1, true>, p, s, prm, par, st, ev0, ev1);
+      }
+    } else {
+      switch (p.ppl) {
+        case 2: launch_scatter_k(k_demand_scatter<2, false>, p, s, prm, par, st, ev0, ev1); break;
+        case 4: launch_scatter_k(k_demand_scatter<4, false>, p, s, prm, par, st, ev0, ev1); break;
+        case 8: launch_scatter_k(k_demand_scatter<8, false>, p, s, prm, par, st, ev0, ev1); break;
+        default: launch_scatter_k(k_demand_scatter<1, false>, p, s, prm, par, st, ev0, ev1);
+      }
     }
     return;
   }
@@ -1988,12 +2060,14 @@ static void launch_link_kernel(const Prob &p, const State &s, const Params *prm,
   }
 }
 
-// dynamic LDS of the privatised-sum demand kernels up to kMaxScatterLinks links (above the default
-// limit of a launch); once per process and device before their first launch
+// dynamic LDS of the privatised-sum demand kernels up to kScatLds bytes (above the default limit of
+// a launch); once per process and device before their first launch
 hipError_t prepare_scatter_kernels() {
-  const int lds = (int)(sizeof(double) * kMaxScatterLinks);
-  const void *ks[] = {(const void *)k_demand_scatter<1>, (const void *)k_demand_scatter<2>,
-                      (const void *)k_demand_scatter<4>, (const void *)k_demand_scatter<8>};
+  const int lds = kScatLds;
+  const void *ks[] = {(const void *)k_demand_scatter<1, false>, (const void *)k_demand_scatter<2, false>,
+                      (const void *)k_demand_scatter<4, false>, (const void *)k_demand_scatter<8, false>,
+                      (const void *)k_demand_scatter<1, true>,  (const void *)k_demand_scatter<2, true>,
+                      (const void *)k_demand_scatter<4, true>,  (const void *)k_demand_scatter<8, true>};
   for (const void *k : ks) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return e;

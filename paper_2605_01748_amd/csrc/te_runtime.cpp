@@ -114,6 +114,10 @@ struct te_ctx {
   int32_t sched_cap = 0;
   int32_t *d_i32 = nullptr;
   int4 *d_wtab = nullptr;
+  uint16_t *d_lent = nullptr;  // link lists of the privatised sums (Prob::lent, lgrp, lchk)
+  int64_t n_lent = 0;          // their entries
+  int2 *d_lgrp = nullptr;
+  int4 *d_lchk = nullptr;
   uint16_t *d_hops = nullptr;
   uint16_t *d_hops2 = nullptr;
   int32_t *d_dovf = nullptr;
@@ -383,11 +387,11 @@ te_status check_options(const te_options *o) {
   if (o->paths_per_lane != 0 && o->paths_per_lane != 1 && o->paths_per_lane != 2 && o->paths_per_lane != 4 &&
       o->paths_per_lane != 8)
     return fail(TE_ERR_INVALID, "paths_per_lane must be 0, 1, 2, 4 or 8");
-  if (o->link_sums < 0 || o->link_sums > 2) return fail(TE_ERR_INVALID, "link_sums must be 0, 1 or 2");
+  if (o->link_sums < 0 || o->link_sums > 3) return fail(TE_ERR_INVALID, "link_sums must be 0, 1, 2 or 3");
   if (o->per_link) {
     if (!(o->w_min > 0.0) || !(o->w_max >= o->w_min) || !(1.0 >= o->w_min) || !(1.0 <= o->w_max))
       return fail(TE_ERR_INVALID, "per_link needs 0 < w_min <= 1 <= w_max");
-    if (o->link_sums == TE_LINK_SUMS_PRIVATE)
+    if (o->link_sums == TE_LINK_SUMS_PRIVATE || o->link_sums == TE_LINK_SUMS_PRIVATE_ATOMIC)
       return fail(TE_ERR_INVALID, "per_link runs with the CSC link sums (link_sums 0 or 2)");
     if (o->record) return fail(TE_ERR_INVALID, "per_link cannot be recorded for te_grad");
     if (o->engine == TE_ENGINE_BLOCK) return fail(TE_ERR_INVALID, "per_link runs on the graph engine");
@@ -449,6 +453,134 @@ int64_t partA_rows(const te_ctx *c) {
   return std::max(csc, scat);
 }
 
+// Link lists of the privatised sums for the launch shape in c->prob (Prob::cpp .. Prob::lchk): the
+// longest chunks of passes whose paths' rates fit the LDS beside the E loads, as even as that
+// count of chunks allows.  A chunk's link runs (the rate slots of its paths on one link) are cut
+// into pieces of at most kPieceLen, sorted by length (longest first, then by link) and dealt 64 to
+// a group, so that the lanes of a group sum pieces of about one length (the chunks of the
+// 1,000-node instance hold runs of 1 to ~2,300 entries, 4 at the median).  cpp = 0 (an LDS atomic
+// addition per incidence) when one pass does not fit or the lists cannot be allocated.
+void build_lists(te_ctx *c) {
+  Prob &p = c->prob;
+  if (c->d_lent) (void)hipFree(c->d_lent);
+  if (c->d_lgrp) (void)hipFree(c->d_lgrp);
+  if (c->d_lchk) (void)hipFree(c->d_lchk);
+  c->d_lent = nullptr;
+  c->d_lgrp = nullptr;
+  c->d_lchk = nullptr;
+  p.cpp = p.cpw = p.zslot = 0;
+  p.lent = nullptr;
+  p.lgrp = nullptr;
+  p.lchk = nullptr;
+  if (c->E > 0x7fff) return;  // link ids of the group headers hold 15 bits
+  const int per = kScatThreads >> c->logGp;
+  const int64_t slots = ((int64_t)kScatLds - 8 * (int64_t)c->E) / 8 - 1;  // one more: the zero slot
+  auto first_path = [&](int64_t ps) { return c->dptr[std::min<int64_t>(ps * per, c->D)]; };
+  // most paths of a chunk when the passes of each workgroup go in chunks of cpp
+  auto most_paths = [&](int cpp) {
+    int64_t m = 0;
+    for (int64_t b = 0; b < p.nF; ++b) {
+      const int64_t pe = std::min<int64_t>((b + 1) * p.spw, p.npass);
+      for (int64_t ps = b * p.spw; ps < pe; ps += cpp)
+        m = std::max<int64_t>(m, first_path(std::min<int64_t>(ps + cpp, pe)) - first_path(ps));
+    }
+    return m;
+  };
+  int cmax = 0;
+  for (int cpp = p.spw; cpp >= 1 && cmax == 0; --cpp)
+    if (most_paths(cpp) <= slots) cmax = cpp;
+  if (cmax == 0) return;
+  const int nch = (p.spw + cmax - 1) / cmax;
+  int cpp = (p.spw + nch - 1) / nch;
+  if (most_paths(cpp) > slots) cpp = cmax;
+  const int cpw = (p.spw + cpp - 1) / cpp;
+  const int32_t zslot = (int32_t)most_paths(cpp);
+  std::vector<int4> chk((size_t)p.nF * cpw, make_int4(0, 0, 0, 0));
+  std::vector<int2> grp;
+  std::vector<uint16_t> ent;
+  ent.reserve((size_t)c->nnz * 9 / 8 + 64);
+  std::vector<int32_t> cnt(c->E, 0), st(c->E, 0), pos(c->E, 0);
+  std::vector<int32_t> run;  // the chunk's rate slots, link after link
+  struct Piece {
+    int32_t len, e, start;
+    bool split;
+  };
+  std::vector<Piece> pc;
+  for (int64_t b = 0; b < p.nF; ++b) {
+    const int64_t pe = std::min<int64_t>((b + 1) * p.spw, p.npass);
+    for (int k = 0; k < cpw; ++k) {
+      const int64_t ps = b * p.spw + (int64_t)k * cpp;
+      const int64_t ps1 = std::min<int64_t>(ps + cpp, pe);
+      int4 &ch = chk[(size_t)b * cpw + k];
+      ch = make_int4((int)grp.size(), (int)grp.size(), 0, 0);
+      if (ps >= ps1) continue;
+      const int32_t r0 = first_path(ps), r1 = first_path(ps1);
+      ch.z = r0;
+      int32_t emin = c->E, emax = -1;
+      for (int32_t i = c->pptr[r0]; i < c->pptr[r1]; ++i) {
+        const int32_t e = c->plinks[i];
+        ++cnt[e];
+        emin = std::min(emin, e);
+        emax = std::max(emax, e);
+      }
+      if (emax < 0) continue;
+      int32_t n = 0;
+      for (int32_t e = emin; e <= emax; ++e) {
+        st[e] = pos[e] = n;
+        n += cnt[e];
+      }
+      run.assign(n, 0);
+      for (int32_t r = r0; r < r1; ++r)  // paths ascending: every run in path order
+        for (int32_t i = c->pptr[r]; i < c->pptr[r + 1]; ++i) run[pos[c->plinks[i]]++] = r - r0;
+      pc.clear();
+      for (int32_t e = emin; e <= emax; ++e)
+        for (int32_t q = 0; q < cnt[e]; q += kPieceLen)
+          pc.push_back({std::min(kPieceLen, cnt[e] - q), e, st[e] + q, cnt[e] > kPieceLen});
+      std::stable_sort(pc.begin(), pc.end(), [](const Piece &x, const Piece &y) { return x.len > y.len; });
+      for (size_t g0 = 0; g0 < pc.size(); g0 += 64) {
+        const int32_t nb = (pc[g0].len + 7) / 8;  // blocks of 8 rows
+        const size_t off = ent.size();
+        if (off + (size_t)(1 + 8 * nb) * 64 > (size_t)INT32_MAX) return;
+        grp.push_back(make_int2((int)off, nb));
+        ent.resize(off + (size_t)(1 + 8 * nb) * 64, (uint16_t)zslot);
+        uint16_t *ge = ent.data() + off;
+        for (int i = 0; i < 64; ++i) {
+          if (g0 + i >= pc.size()) {
+            ge[i] = 0xffff;  // no piece
+            continue;
+          }
+          const Piece &q = pc[g0 + i];
+          ge[i] = (uint16_t)(q.e | (q.split ? 0x8000 : 0));
+          for (int32_t j = 0; j < q.len; ++j) ge[64 + 512 * (j / 8) + 8 * i + (j % 8)] = (uint16_t)run[q.start + j];
+        }
+      }
+      ch.y = (int)grp.size();
+      for (int32_t e = emin; e <= emax; ++e) cnt[e] = 0;
+    }
+  }
+  if (grp.empty() || dalloc(&c->d_lent, ent.size()) != hipSuccess || dalloc(&c->d_lgrp, grp.size()) != hipSuccess ||
+      dalloc(&c->d_lchk, chk.size()) != hipSuccess ||
+      hipMemcpy(c->d_lent, ent.data(), sizeof(uint16_t) * ent.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_lgrp, grp.data(), sizeof(int2) * grp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_lchk, chk.data(), sizeof(int4) * chk.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipGetLastError();
+    void *bufs[] = {c->d_lent, c->d_lgrp, c->d_lchk};
+    for (void *q : bufs)
+      if (q) (void)hipFree(q);
+    c->d_lent = nullptr;
+    c->d_lgrp = nullptr;
+    c->d_lchk = nullptr;
+    return;
+  }
+  c->n_lent = (int64_t)ent.size();
+  p.cpp = cpp;
+  p.cpw = cpw;
+  p.zslot = zslot;
+  p.lent = c->d_lent;
+  p.lgrp = c->d_lgrp;
+  p.lchk = c->d_lchk;
+}
+
 // Launch shape of the graph engine for ppl paths per lane and link sums lsum (kLinkSums*).
 // Privatised sums: passes of kScatThreads / 2^logGp demands, dealt in runs of spw consecutive
 // passes to at most one scatter workgroup per compute unit (each holds the E loads in LDS).
@@ -461,8 +593,9 @@ void set_graph_shape(te_ctx *c, int ppl, int lsum) {
   Prob &p = c->prob;
   p.ppl = c->ppl;
   p.logGp = c->logGp;
-  p.lsum = lsum;
-  if (lsum == kLinkSumsPrivate) {
+  const bool priv = lsum == kLinkSumsPrivate || lsum == kLinkSumsPrivateAtomic;
+  p.lsum = priv ? kLinkSumsPrivate : lsum;
+  if (priv) {
     const int per = kScatThreads >> c->logGp;
     p.npass = (c->D + per - 1) / per;
     p.spw = (p.npass + c->ncu - 1) / c->ncu;
@@ -470,8 +603,14 @@ void set_graph_shape(te_ctx *c, int ppl, int lsum) {
     c->st.nA = p.nF;
     c->st.nArows = p.nF * (kScatThreads / 64);
     c->st.nB = (c->E + 63) / 64;
+    if (lsum == kLinkSumsPrivate) {
+      build_lists(c);
+    } else {
+      p.cpp = 0;
+    }
   } else {
     p.npass = p.spw = p.nF = 0;
+    p.cpp = 0;
     c->st.nA = (c->D + (kThreads >> c->logGp) - 1) / (kThreads >> c->logGp);
     c->st.nArows = c->st.nA * (kThreads / 64);
     c->st.nB = c->nB_csc;
@@ -494,7 +633,7 @@ te_status select_graph_shape(te_ctx *c, const te_options &o) {
   const int want = o.paths_per_lane ? o.paths_per_lane : default_graph_ppl(c);
   int lsum = o.link_sums ? o.link_sums : default_link_sums(c);
   if (o.per_link) lsum = kLinkSumsCsc;  // the per-link rule needs per-link sums of (x' - x)^2
-  if (lsum == kLinkSumsPrivate && c->E > kMaxScatterLinks)
+  if ((lsum == kLinkSumsPrivate || lsum == kLinkSumsPrivateAtomic) && c->E > kMaxScatterLinks)
     return fail(TE_ERR_INVALID, "privatised link sums hold at most %d links (instance: %d)", kMaxScatterLinks, c->E);
   if (want == c->ppl && lsum == c->lsum) return TE_OK;
   HIPCHK(hipDeviceSynchronize());  // no launch of the old graphs may still be in flight
@@ -853,6 +992,9 @@ te_status te_info(const te_ctx *c, int64_t *sz) {
   sz[9] = c->rec_K > 0 ? c->rec_gen : 0;
   sz[10] = c->lsum;
   sz[11] = c->prob.nF;
+  const bool lists = c->prob.lsum == kLinkSumsPrivate && c->prob.cpp > 0;
+  sz[12] = lists ? c->prob.cpp : 0;
+  sz[13] = lists ? c->n_lent : 0;
   return TE_OK;
 }
 
@@ -1318,7 +1460,7 @@ void te_destroy(te_ctx *c) {
   free_fwd(c->work);
   void *bufs[] = {c->d_i32, c->d_Dn, c->d_Cn, c->d_trace, c->st.partL, c->st.w, c->st.dx2, c->st.ctrl,
                   c->st.partA, c->st.partB, c->pb.xd, c->pb.S, c->pb.L, c->pb.Cp, c->pb.lsc, c->pb.trim,
-                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops, c->d_hops2, c->d_dovf};
+                  c->d_params, c->d_desc, c->d_bout, c->d_sched, c->d_wtab, c->d_hops, c->d_hops2, c->d_dovf, c->d_lent, c->d_lgrp, c->d_lchk};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   if (c->h_params) (void)hipHostFree(c->h_params);

@@ -64,9 +64,11 @@ def test_layout_bytes_by_counting():
     for hop in (0, 4):
         ids = 2 * nnz if hop else 4 * (P + 1) + 4 * nnz
         base = ids + (8 + 8) * 2 * P + 16 * E + (4 + 8 + 2 * 8 + 2 * 8) * D
-        priv = dict(hop_slots=hop, link_sums=1, scatter_workgroups=3)
+        priv = dict(hop_slots=hop, link_sums=3, scatter_workgroups=3, list_entries=0)
         rows = 3 * 8 * E
         assert bench.layout_bytes(inst, priv) == (base + rows, rows + 2 * 16 * E + 8 * E + 8 * E)
+        lists = dict(hop_slots=hop, link_sums=1, scatter_workgroups=3, list_entries=640)
+        assert bench.layout_bytes(inst, lists) == (base + rows + 2 * 640, rows + 2 * 16 * E + 8 * E + 8 * E)
         csc = dict(hop_slots=hop, link_sums=2, scatter_workgroups=0)
         assert bench.layout_bytes(inst, csc) == (base, 4 * nnz + 8 * P + 2 * 16 * E + 8 * E + 8 * E)
 

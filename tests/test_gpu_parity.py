@@ -420,7 +420,7 @@ def test_parity_graph_paths_per_lane(te, c1, c2, ppl, name):
 
 def test_invalid_options_rejected(te, c1):
     prob = te.Problem(c1)
-    for bad in (dict(beta0=-1.0), dict(block_threads=128), dict(paths_per_lane=3)):
+    for bad in (dict(beta0=-1.0), dict(block_threads=128), dict(paths_per_lane=3), dict(link_sums=4)):
         with pytest.raises(te.TEError) as ex:
             prob.solve(te.Options(**bad))
         assert ex.value.status == te.TE_ERR_INVALID
@@ -758,26 +758,29 @@ _LSUM_CASES = {
 
 
 @pytest.mark.parametrize("ppl", [0, 2])
-@pytest.mark.parametrize("lsum", ["private", "csc"])
+@pytest.mark.parametrize("lsum", ["private", "private_atomic", "csc"])
 @pytest.mark.parametrize("name", sorted(_LSUM_CASES))
 def test_parity_link_sum_variants(te, name, lsum, ppl):
-    """Both ways of forming the link loads (privatised LDS rows reduced per link, or segmented sums
-    over the link -> path list) against the oracle, schedule replayed, on instances with 1 to 64 paths
-    per demand and hop-record or CSR path layouts; the handle switches between them; one and two
-    paths per lane."""
+    """The ways of forming the link loads (privatised LDS rows reduced per link, summed by link lists
+    or by one atomic addition per incidence, or segmented sums over the link -> path list) against the
+    oracle, schedule replayed, on instances with 1 to 64 paths per demand and hop-record or CSR path
+    layouts; the handle switches between them; one and two paths per lane."""
     inst = _LSUM_CASES[name]()
     K = 64
     r, sb, sa = _oracle_run(inst, K)
     prob = te.Problem(inst)
-    want = te.LINK_SUMS_PRIVATE if lsum == "private" else te.LINK_SUMS_CSC
-    other = te.LINK_SUMS_CSC if lsum == "private" else te.LINK_SUMS_PRIVATE
+    want = {"private": te.LINK_SUMS_PRIVATE, "private_atomic": te.LINK_SUMS_PRIVATE_ATOMIC,
+            "csc": te.LINK_SUMS_CSC}[lsum]
+    other = te.LINK_SUMS_CSC if lsum != "csc" else te.LINK_SUMS_PRIVATE
     for ls in (want, other, want):
         x, S, st = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, link_sums=ls,
                                          paths_per_lane=ppl, sched_beta=sb, sched_alpha=sa))
         info = prob.info()
         assert info["link_sums"] == ls
         assert (info["hop_slots"] == 0) == (name == "ragged_long")
-        assert (info["scatter_workgroups"] > 0) == (ls == te.LINK_SUMS_PRIVATE)
+        assert (info["scatter_workgroups"] > 0) == (ls != te.LINK_SUMS_CSC)
+        assert (info["list_passes"] > 0) == (ls == te.LINK_SUMS_PRIVATE)
+        assert (info["list_entries"] >= inst.nnz) == (ls == te.LINK_SUMS_PRIVATE)
         err = _report(f"{name} link sums {ls} K={K}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
                       inst.demand)
         assert err.max() <= REL
@@ -836,7 +839,8 @@ def test_per_link_penalties_match_oracle(te, name, K):
 def test_per_link_refused_where_unsupported(te, c1):
     prob = te.Problem(c1)
     for bad in (dict(engine=te.ENGINE_BLOCK), dict(record=True, fixed_iters=8),
-                dict(link_sums=te.LINK_SUMS_PRIVATE), dict(w_min=2.0)):
+                dict(link_sums=te.LINK_SUMS_PRIVATE), dict(link_sums=te.LINK_SUMS_PRIVATE_ATOMIC),
+                dict(w_min=2.0)):
         with pytest.raises(te.TEError) as ex:
             prob.solve(te.Options(per_link=True, **{"fixed_iters": 8, **bad}))
         assert ex.value.status == te.TE_ERR_INVALID
