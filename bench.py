@@ -247,6 +247,7 @@ def large_run(args, torch, te, W, dev, with_oracle=True):
            "n_links": inst.n_links, "n_demands": inst.n_demands, "n_paths": inst.n_paths, "nnz": inst.nnz,
            "ms_per_iteration": round(ms_iter, 4), "demand_paths_per_lane": st64["paths_per_lane"],
            "link_sums": LINK_SUMS_NAME[info["link_sums"]], "list_passes": info["list_passes"],
+           "list_entries": info["list_entries"],
            "scatter_workgroups": info["scatter_workgroups"], "hop_slots": info["hop_slots"],
            "per_iteration": it, "kernels": kr, "error_vs_fp64_oracle": err}
     del prob
