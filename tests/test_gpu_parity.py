@@ -801,6 +801,24 @@ def test_link_sums_limit(te):
     assert ex.value.status == te.TE_ERR_INVALID
 
 
+@pytest.mark.parametrize("n_links,lists", [(17000, True), (19400, False)])
+def test_link_lists_need_room_beside_the_loads(te, n_links, lists):
+    """Privatised sums keep a chunk of rates in LDS beside the E loads: with 17,000 links a pass of
+    rates still fits and the link lists are used; with 19,400 it does not, and the same option adds one
+    incidence at a time. Both against the oracle, schedule replayed."""
+    inst = W.ragged(3, n_links=n_links, n_demands=60)
+    prob = te.Problem(inst)
+    r, sb, sa = _oracle_run(inst, 16)
+    x, S, st = prob.solve(te.Options(fixed_iters=16, project=False, engine=te.ENGINE_GRAPH,
+                                     link_sums=te.LINK_SUMS_PRIVATE, sched_beta=sb, sched_alpha=sa))
+    info = prob.info()
+    assert info["link_sums"] == te.LINK_SUMS_PRIVATE and info["scatter_workgroups"] > 0
+    assert (info["list_passes"] > 0) == lists
+    err = _report(f"ragged E={n_links} private link sums", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
+                  inst.demand)
+    assert err.max() <= REL
+
+
 def test_state_is_the_fp64_iterate(te, c1):
     """te_get_state returns the FP64 rates of the last graph-engine solve: their FP32 rounding is the
     unprojected output, and their per-demand sums are the output sums."""
