@@ -73,6 +73,16 @@ def test_layout_bytes_by_counting():
         assert bench.layout_bytes(inst, csc) == (base, 4 * nnz + 8 * P + 2 * 16 * E + 8 * E + 8 * E)
 
 
+def test_profiled_kernel_names():
+    """The names rocprofv3 gives the per-iteration kernels (template arguments included), which key the
+    traffic summaries under profiles/."""
+    assert bench.profiled_name("k_demand", 1) == "k_demand"
+    assert bench.profiled_name("k_demand", 2) == "k_demand_multi<2>"
+    assert bench.profiled_name("k_demand_scatter", 2, True) == "k_demand_scatter<2, true>"
+    assert bench.profiled_name("k_demand_scatter", 1, False) == "k_demand_scatter<1, false>"
+    assert bench.profiled_name("k_link_reduce", 2, True) == "k_link_reduce"
+
+
 def test_roofline_fractions():
     inst = W.parking_lot(3)
     info = dict(hop_slots=4, link_sums=1, scatter_workgroups=2)
