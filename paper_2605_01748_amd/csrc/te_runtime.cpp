@@ -468,6 +468,7 @@ void build_lists(te_ctx *c) {
   c->d_lent = nullptr;
   c->d_lgrp = nullptr;
   c->d_lchk = nullptr;
+  c->n_lent = 0;
   p.cpp = p.cpw = p.zslot = 0;
   p.lent = nullptr;
   p.lgrp = nullptr;
