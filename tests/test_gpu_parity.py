@@ -819,6 +819,31 @@ def test_link_lists_need_room_beside_the_loads(te, n_links, lists):
     assert err.max() <= REL
 
 
+def test_link_lists_in_uneven_chunks(te, torch):
+    """600,000 one-path demands over 17,000 links: passes of 1,024 demands, three a scatter workgroup
+    (256 compute units), of which two fit beside the loads, so a workgroup sums its lists after passes
+    2 and 3 (chunks of two and one) and the last workgroup has a single pass. Against the oracle,
+    schedule replayed."""
+    inst = W.single_paths(0)
+    K = 8
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    x, S, st = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH,
+                                     link_sums=te.LINK_SUMS_PRIVATE, sched_beta=sb, sched_alpha=sa))
+    info = prob.info()
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    npass = -(-inst.n_demands // 1024)
+    spw = -(-npass // ncu)
+    print(f"compute units {ncu}, passes {npass}, {spw} a workgroup, {info['list_passes']} a chunk")
+    assert info["scatter_workgroups"] == -(-npass // spw)
+    assert 1 <= info["list_passes"] <= spw and info["list_entries"] >= inst.nnz
+    if ncu == 256:
+        assert spw == 3 and info["list_passes"] == 2
+    err = _report("single paths private link sums", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
+                  inst.demand)
+    assert err.max() <= REL
+
+
 def test_state_is_the_fp64_iterate(te, c1):
     """te_get_state returns the FP64 rates of the last graph-engine solve: their FP32 rounding is the
     unprojected output, and their per-demand sums are the output sums."""

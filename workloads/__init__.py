@@ -580,6 +580,29 @@ def parallel_paths(caps, demand) -> Instance:
     return make_instance("parallel", 2, [0] * m, [1] * m, caps, [0], [1], [demand], [[[i] for i in range(m)]])
 
 
+def single_paths(seed: int = 0, n_links: int = 17000, n_demands: int = 600000) -> Instance:
+    """Edge-case instance for the privatised link sums' chunking (not a network): many demands of one
+    path each, of 1 to 3 distinct links drawn uniformly, capacities in {1, 4, 10} x 100, demands
+    log-uniform over two orders of magnitude.  Built without per-demand Python lists (vectorised)."""
+    rng = np.random.default_rng(np.random.SeedSequence([11, seed]))
+    hops = rng.integers(1, 4, size=n_demands)
+    base = rng.integers(0, n_links, size=n_demands)
+    off1 = rng.integers(1, n_links // 2, size=n_demands)
+    off2 = off1 + rng.integers(1, n_links // 2, size=n_demands)  # 0 < off1 < off2 < n_links: distinct links
+    cand = np.stack([base, (base + off1) % n_links, (base + off2) % n_links], axis=1)
+    keep = np.arange(3)[None, :] < hops[:, None]
+    links = cand[keep].astype(np.int32)  # row-major: each demand's first hops links, in order
+    path_ptr = np.concatenate([[0], np.cumsum(hops)]).astype(np.int64)
+    cap = 100.0 * rng.choice([1.0, 4.0, 10.0], size=n_links)
+    demand = 10.0 ** rng.uniform(-1.0, 1.0, n_demands)
+    src = np.arange(n_links, dtype=np.int32)
+    return Instance(name=f"single_paths/s{seed}", n_nodes=n_links + 1, link_src=src, link_dst=src + 1,
+                    capacity=cap, demand_src=np.zeros(n_demands, np.int32), demand_dst=np.ones(n_demands, np.int32),
+                    demand=demand, path_ptr=path_ptr, path_links=links,
+                    demand_path_ptr=np.arange(n_demands + 1, dtype=np.int32),
+                    meta=dict(kind="single_paths", seed=seed))
+
+
 def ragged(seed: int = 0, n_links: int = 48, n_demands: int = 40, max_hops: int = 12) -> Instance:
     """Edge-case instance for the kernels' boundaries (not a network): demands with 1, 2, 3, 5, 8, 17,
     33 and 64 paths (64 is the per-demand maximum), paths of 1 to max_hops links (12: beyond the 8-hop
