@@ -145,3 +145,23 @@ def test_drift_path_keeps_unused_links_at_zero():
     s = W.drift_path(inst, [3600.0], seed=1, cap_events_per_day=86400.0)[0]
     assert np.all(s.capacity[inst.capacity == 0.0] == 0.0)
     assert s.meta["drift"]["cap_events"] > 0
+
+
+def test_single_paths_shape():
+    inst = W.single_paths(1, n_links=500, n_demands=20000)
+    assert inst.n_demands == 20000 and inst.n_paths == 20000
+    np.testing.assert_array_equal(inst.demand_path_ptr, np.arange(20001))
+    hops = np.diff(inst.path_ptr)
+    assert hops.min() == 1 and hops.max() == 3 and inst.nnz == hops.sum()
+    pl = inst.path_links
+    assert pl.min() >= 0 and pl.max() < 500
+    # the links of a path are distinct
+    for h in (2, 3):
+        rows = np.flatnonzero(hops == h)
+        ids = pl[inst.path_ptr[rows][:, None] + np.arange(h)[None, :]]
+        assert np.all(ids[:, 0] != ids[:, 1])
+        if h == 3:
+            assert np.all((ids[:, 2] != ids[:, 0]) & (ids[:, 2] != ids[:, 1]))
+    again = W.single_paths(1, n_links=500, n_demands=20000)
+    np.testing.assert_array_equal(again.path_links, pl)
+    np.testing.assert_array_equal(again.demand, inst.demand)
