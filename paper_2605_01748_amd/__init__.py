@@ -138,7 +138,7 @@ class Options:
     paths_per_lane: int = 0            # 1, 2, 4, 8; 0 = graph engine default, workgroup engine tuned
     warm: bool = False                 # continue from the handle's last graph-engine state
     trace: bool = False                # log (beta_k, alpha_k, r_k, s_k) per iteration (Problem.trace)
-    link_sums: int = LINK_SUMS_AUTO    # graph engine: privatised (LDS rows) or CSC segmented link sums
+    link_sums: int = LINK_SUMS_AUTO    # graph engine: privatised (LDS rows; link lists or atomic adds) or CSC sums
     per_link: bool = False             # per-link adaptive penalties beta * w_e (graph engine, CSC sums)
     w_min: float = 0.25
     w_max: float = 4.0
