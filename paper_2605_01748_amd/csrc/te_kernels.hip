@@ -671,7 +671,7 @@ __device__ __forceinline__ void add_slots(const double *xs, uint4 q, double &v0,
   v1 += xs[q.w >> 16];
 }
 
-// the sum v of lane's piece of a group goes to acc at the piece's link: an atomic addition where the
+// the sum v of a lane's piece of a group goes to acc at the piece's link: an atomic addition where the
 // link has other pieces, else a plain one (no other lane of the workgroup adds to it in the chunk)
 __device__ __forceinline__ void add_piece(unsigned lk, double v, double *acc) {
   if (lk == 0xffffu) return;
@@ -970,11 +970,11 @@ __device__ __forceinline__ void scatter_ids(const Prob &p, const PathIds &id, do
   }
 }
 
-// With link lists (p.cpp > 0) the new rates of a chunk of passes go to LDS, and after the chunk the
-// workgroup sums them per link over the chunk's list (one LDS addition per piece of a link's run,
-// not one per incidence).  Without,
-// every incidence is an LDS atomic addition; KEEP: the gather's link ids stay in registers for it
-// (one path per lane), or are read again (several paths per lane, where keeping them would spill).
+// LISTS (link lists, p.cpp > 0): the new rates of a chunk of passes go to LDS, and after the chunk
+// the workgroup sums them per link over the chunk's list (one LDS addition per piece of a link's
+// run, not one per incidence).  Without: every incidence is an LDS atomic addition; KEEP: the
+// gather's link ids stay in registers for it (one path per lane), or are read again (several paths
+// per lane, where keeping them would spill).
 template <int PPL, bool LISTS>
 __global__ __launch_bounds__(kScatThreads) void k_demand_scatter(Prob p, State s, const Params *prmp, int par) {
   constexpr bool KEEP = PPL == 1 && !LISTS;
