@@ -786,6 +786,26 @@ def test_parity_link_sum_variants(te, name, lsum, ppl):
         assert err.max() <= REL
 
 
+@pytest.mark.parametrize("ppl", [4, 8])
+@pytest.mark.parametrize("lsum", ["private", "private_atomic"])
+@pytest.mark.parametrize("name", ["ragged0", "parallel_64", "two_level_6"])
+def test_parity_private_sums_many_paths_per_lane(te, name, lsum, ppl):
+    """The privatised sums' kernels with four and eight paths per lane (link lists and atomic adds)
+    against the oracle, schedule replayed."""
+    inst = _LSUM_CASES[name]()
+    K = 32
+    r, sb, sa = _oracle_run(inst, K)
+    prob = te.Problem(inst)
+    ls = te.LINK_SUMS_PRIVATE if lsum == "private" else te.LINK_SUMS_PRIVATE_ATOMIC
+    x, S, st = prob.solve(te.Options(fixed_iters=K, project=False, engine=te.ENGINE_GRAPH, link_sums=ls,
+                                     paths_per_lane=ppl, sched_beta=sb, sched_alpha=sa))
+    assert st["paths_per_lane"] == ppl
+    assert (prob.info()["list_passes"] > 0) == (lsum == "private")
+    err = _report(f"{name} link sums {ls} ppl {ppl} K={K}", S.cpu().numpy().astype(np.float64), r.S_raw * r.scale,
+                  inst.demand)
+    assert err.max() <= REL
+
+
 def test_link_sums_limit(te):
     """More links than one workgroup's LDS holds: the automatic choice is the CSC sums, and asking for
     privatised sums is refused."""
